@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the restarted PDHG hot path on one MI355X.
+
+Workload: the power-law LP m=200k, n=1M, nnz~9.4M (column counts ~ k^-2.1
+on [2, 5000], values N(0,1)*10^U(-2,2), planted optimum), FP64, Ruiz 10
+passes, target relative KKT 1e-8.  One step = one batch of eval_every (64)
+PDHG iterations (fused primal step + extrapolated dual step + averages) and
+its FP64 KKT evaluation with the restart / snapshot / stop decisions, i.e.
+every stage of the hot path.  value = PDHG iterations per second over the
+timed steps with all data resident in HBM.
+
+Also reported (outside the timed region): per-kernel HIP-event durations
+and the algorithmic HBM bandwidth of the dominant kernel (roofline), the
+CPU oracle on a bounded sample (cpu_baseline), and the time to relative KKT
+1e-8 of the FP64 path and of FP32 bulk iterations with FP64 refinement.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("PDHG iters/s + HBM GB/s; time to rel KKT 1e-8, FP32+refine vs "
+          "FP64, 1 GPU")
+HBM_PEAK_GBS = 8000.0
+
+
+def alg_bytes(m: int, n: int, nnz: int, fp: int = 8, has_l: bool = False):
+    """Algorithmic HBM bytes of one primal and one dual step.
+
+    Each step streams its CSR (values fp bytes + 4-byte column index per
+    nonzero, 4-byte row pointers), gathers the other side's vector once, and
+    reads / writes its own vectors once.
+      primal (rows of A^T): x, c, xbar read; x, xbar written (+ l read)
+      dual   (rows of A):   y, b, A~x, ybar read; y, A~x, ybar written
+    """
+    primal = (fp + 4) * nnz + 4 * (n + 1) + fp * m + 5 * fp * n + (fp * n if has_l else 0)
+    dual = (fp + 4) * nnz + 4 * (m + 1) + fp * n + 7 * fp * m
+    return primal, dual
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="powerlaw_m200k_n1m")
+    ap.add_argument("--no-ttk", action="store_true", help="skip time-to-KKT runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle")
+    ap.add_argument("--ttk-cap", type=float, default=90.0,
+                    help="seconds allowed per time-to-KKT run")
+    ap.add_argument("--cpu-iters", type=int, default=64)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the multi-GPU sharding is a design note only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_24429_amd import lpgen
+    from paper_2510_24429_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    lp = lpgen.make(args.workload)
+    print(f"[bench] generated {args.workload}: m={lp.m} n={lp.n} nnz={lp.nnz} "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    N = 64
+    s = Solver.from_lp(lp, device=0)
+    s.configure(eps_rel=1e-8, eval_every=N, use_graph=0 if args.no_graph else 1)
+    print(f"[bench] configured ({s.info()['t_setup']:.2f}s setup)",
+          file=sys.stderr, flush=True)
+
+    restarts_of_run = 0
+
+    def step():
+        nonlocal restarts_of_run
+        st = s.iterate(N)
+        if st != 0:        # converged inside the window: start over
+            restarts_of_run += 1
+            s.set_iterate(None, None)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    elapsed = tb - ta
+    iters = args.steps * N
+    value = iters / elapsed
+    print(f"[bench] timed {args.steps} steps: {elapsed:.3f}s, {value:.1f} iters/s",
+          file=sys.stderr, flush=True)
+
+    # per-kernel durations with HIP events on the library's stream
+    s.profile(True)
+    s.kernel_times(reset=True)
+    for _ in range(max(5, min(20, args.steps))):
+        step()
+    kt = s.kernel_times(reset=True)
+    s.profile(False)
+    bp, bd = alg_bytes(lp.m, lp.n, lp.nnz)
+    tp = kt["primal_step"]["total_ms"] / max(kt["primal_step"]["launches"], 1)
+    td = kt["dual_step"]["total_ms"] / max(kt["dual_step"]["launches"], 1)
+    gbs_p = bp / (tp * 1e-3) / 1e9
+    gbs_d = bd / (td * 1e-3) / 1e9
+    dominant = "primal_step" if tp >= td else "dual_step"
+    ach = gbs_p if dominant == "primal_step" else gbs_d
+    iter_gbs = (bp + bd) / ((tp + td) * 1e-3) / 1e9
+    print(f"[bench] primal {tp*1e3:.1f}us {gbs_p:.0f}GB/s  dual {td*1e3:.1f}us "
+          f"{gbs_d:.0f}GB/s  iteration {iter_gbs:.0f}GB/s", file=sys.stderr, flush=True)
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == _kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator, planted optimum)",
+        "config": {"workload": args.workload, "m": lp.m, "n": lp.n,
+                   "nnz": lp.nnz, "precision": "fp64", "eval_every": N,
+                   "ruiz_passes": 10, "eps_rel": 1e-8,
+                   "graphs": not args.no_graph},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": dominant},
+        "kernels": {"primal_step": {"us": round(tp * 1e3, 2), "alg_bytes": bp,
+                                    "GB_s": round(gbs_p, 1)},
+                    "dual_step": {"us": round(td * 1e3, 2), "alg_bytes": bd,
+                                  "GB_s": round(gbs_d, 1)},
+                    "iteration_GB_s": round(iter_gbs, 1),
+                    "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)},
+        "restarts_of_run": restarts_of_run,
+    }
+
+    if not args.no_ttk:
+        out["time_to_kkt"] = time_to_kkt(Solver, lp, args.ttk_cap)
+
+    s.close()
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters)
+
+    print(json.dumps(out), flush=True)
+
+
+def _kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2510_24429_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_to_kkt(Solver, lp, cap):
+    """Wall time from data resident on the GPU (after load) to FP64 relative
+    KKT <= 1e-8: FP64 path vs FP32 bulk + FP64 refinement."""
+    import torch
+    res = {}
+    with Solver.from_lp(lp, device=0) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.configure(eps_rel=1e-8, time_limit_s=cap)
+        st = s.solve()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        inf = s.info()
+        res["fp64"] = {"seconds": round(t, 3), "status": st, "iters": inf["iters"],
+                       "restarts": inf["restarts"],
+                       "maxresid": inf["kkt"]["maxresid"]}
+        print(f"[bench] ttk fp64: {t:.2f}s status {st} iters {inf['iters']} "
+              f"maxresid {inf['kkt']['maxresid']:.2e}", file=sys.stderr, flush=True)
+    with Solver.from_lp(lp, device=0) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.configure(eps_rel=1e-8, time_limit_s=cap)
+        r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res["fp32_refine"] = {"seconds": round(t, 3), "status": r["status"],
+                              "rounds": r["rounds"], "inner_iters": r["inner_iters"],
+                              "maxresid": r["kkt"]["maxresid"]}
+        print(f"[bench] ttk fp32+refine: {t:.2f}s status {r['status']} rounds "
+              f"{r['rounds']} inner iters {r['inner_iters']} maxresid "
+              f"{r['kkt']['maxresid']:.2e}", file=sys.stderr, flush=True)
+    if res["fp64"]["status"] == 1 and res["fp32_refine"]["status"] == 1:
+        res["speedup_fp32_refine"] = round(res["fp64"]["seconds"] /
+                                           res["fp32_refine"]["seconds"], 3)
+    return res
+
+
+def cpu_baseline(lp, iters):
+    """The FP64 oracle, serial, on the same LP: `iters` iterations (with its
+    evaluations at k = 0 and every 64), setup (Ruiz, scaling) excluded."""
+    from oracle import oracle
+    t0 = time.time()
+    r = oracle.solve(lp, eps_rel=1e-8, max_iters=iters, eta=0.5, omega0=1.0)
+    wall = time.time() - t0
+    ips = r.info["iters"] / r.info["t_iter"]
+    print(f"[bench] cpu oracle: {r.info['iters']} iters in {r.info['t_iter']:.2f}s "
+          f"(setup {r.info['t_setup']:.2f}s, wall {wall:.1f}s)", file=sys.stderr,
+          flush=True)
+    return {"value": round(ips, 3), "unit": "iters/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{r.info['iters']} PDHG iterations of the same LP incl. "
+                      f"evaluations at k=0 and every 64, setup excluded, 1 thread"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,338 @@
+/*
+ * pdhg.h -- C ABI of libpdhg.so, an MI355X (gfx950) implementation of the
+ * restarted, diagonally preconditioned PDHG iteration for the standard-form LP
+ *
+ *     min c^T x   s.t.  A x = b,  x >= l      (l = 0 unless set)
+ *     max b^T y + l^T z   s.t.  A^T y + z = c,  z >= 0
+ *
+ * (the primal/dual pair of Section 2 of Rothberg, "Concurrent Crossover for
+ * PDHG", with an optional lower-bound vector used by iterative refinement).
+ *
+ * Conventions for every call:
+ *  - Return value: PDHG_OK (0) or a negative pdhg_error; the message is in
+ *    pdhg_last_error(ctx).  No C++ exception crosses this boundary.  Solver
+ *    outcomes (converged, iteration limit, ...) are reported separately as a
+ *    pdhg_status through an out-parameter.
+ *  - `mem` says where caller pointers live: PDHG_MEM_HOST (pageable or pinned
+ *    host memory) or PDHG_MEM_DEVICE (device memory of the context's GPU, for
+ *    example a torch tensor's data_ptr()).  Device pointers are used only
+ *    during the call and ordered on the context's stream; the call returns
+ *    after the stream has finished with them.
+ *  - Inputs are copied: the library owns its device copies, the caller may
+ *    free or reuse its arrays when the call returns.  Output buffers belong
+ *    to the caller and must hold the stated number of elements.
+ *  - Index arrays: row pointers int64 (m+1 or n+1 entries, first 0, last nnz,
+ *    non-decreasing), column indices int32 in [0, ncols), strictly increasing
+ *    inside a row.  nnz must stay below 2^31.  Values are IEEE binary64.
+ *  - A context is not thread-safe; only pdhg_cancel may be called from
+ *    another thread while a call on the same context runs.
+ *  - The library allocates its device buffers itself (hipMalloc) at load and
+ *    configure time and frees them in pdhg_destroy.
+ */
+#ifndef PDHG_H
+#define PDHG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdhg_ctx pdhg_ctx;
+typedef struct pdhg_tape pdhg_tape;
+
+/* Error codes: the call failed and changed nothing the caller relies on. */
+enum pdhg_error {
+    PDHG_OK = 0,
+    PDHG_E_ARG = -1,        /* bad argument (null pointer, size, range) */
+    PDHG_E_CSR = -2,        /* malformed CSR arrays */
+    PDHG_E_TRANSPOSE = -3,  /* A^T is not the transpose of A (values bitwise) */
+    PDHG_E_DEVICE = -4,     /* a HIP runtime call failed */
+    PDHG_E_OOM = -5,        /* host or device allocation failed */
+    PDHG_E_STATE = -6       /* call out of order (e.g. iterate before load) */
+};
+
+/* Solver status: the call succeeded; this says where the iteration stands. */
+enum pdhg_status {
+    PDHG_RUNNING = 0,
+    PDHG_CONVERGED = 1,     /* maxresid <= eps_rel (Section 2 criteria) */
+    PDHG_ITER_LIMIT = 2,
+    PDHG_TIME_LIMIT = 3,
+    PDHG_CANCELLED = 4,
+    PDHG_NUMERICAL = 5      /* a KKT quantity became NaN or infinite */
+};
+
+enum { PDHG_MEM_HOST = 0, PDHG_MEM_DEVICE = 1 };
+
+/* Arithmetic of the bulk iteration (SpMVs and fused vector updates).  The
+ * KKT reductions, restart decisions and refinement update are FP64 always. */
+enum { PDHG_FP64 = 0, PDHG_FP32 = 1 };
+
+/*
+ * Solver parameters.  The paper fixes the stopping rule (the three relative
+ * inequalities of Section 2) and the snapshot schedule (Algorithm 1,
+ * Section 3.1: a snapshot whenever maxresid <= eps_target, then a tenfold
+ * smaller target, until eps_rel).  It states no PDHG internals; the defaults
+ * of the remaining fields are the published PDLP-style choices.
+ */
+typedef struct {
+    int32_t precision;          /* PDHG_FP64 (default) or PDHG_FP32 */
+    int32_t ruiz_passes;        /* Ruiz l_inf equilibration passes (10) */
+    int32_t power_iters;        /* power-iteration steps for ||A~||_2 (100) */
+    int32_t eval_every;         /* iterations between KKT evaluations (64) */
+    int32_t literal_snapshots;  /* 1: at most one level per evaluation, as
+                                   Algorithm 1 checks one target at a time */
+    int32_t n_levels;           /* number of snapshot tolerances (<= 32) */
+    const double *levels;       /* strictly descending, copied at configure */
+    double eps_rel;             /* stop when maxresid <= eps_rel (1e-6) */
+    double eta;                 /* step size; <= 0: eta_factor / sigma_hat */
+    double omega0;              /* initial primal weight; <= 0: ||c~||/||b~|| */
+    double eta_factor;          /* 0.9 */
+    double beta_suff;           /* restart if KKT <= beta_suff * KKT_last (0.2) */
+    double beta_nec;            /* ... or <= beta_nec * KKT_last and rising (0.8) */
+    double beta_art;            /* ... or t >= beta_art * k (0.36) */
+    double omega_theta;         /* primal-weight smoothing (0.5) */
+    int64_t max_iters;          /* total iteration limit */
+    double time_limit_s;        /* wall-clock limit per solve (3600) */
+    int32_t use_graph;          /* replay eval_every-iteration batches as hipGraphs */
+    int32_t pad_;
+} pdhg_params;
+
+/* Relative KKT errors of an unscaled iterate on the original data:
+ * rel_p = ||b - Ax||_2 / (1 + ||b||_2), rel_d = ||r_D||_2 / (1 + ||c||_2)
+ * with z = max(0, c - A^T y) and r_D = A^T y + z - c, rel_gap =
+ * |pobj - dobj| / (1 + |pobj| + |dobj|), maxresid = max of the three
+ * (Section 2's three inequalities; maxresid of Algorithm 1). */
+typedef struct {
+    double rel_p, rel_d, rel_gap, maxresid;
+    double pobj, dobj;          /* c^T x and b^T y + l^T z */
+    double norm_rp, norm_rd;    /* ||r_P||_2, ||r_D||_2 */
+    double rp_inf, rd_inf;      /* max-norms (informational) */
+    int64_t iter;
+    int32_t candidate;          /* 0 current iterate, 1 average */
+    int32_t pad_;
+} pdhg_kkt;
+
+typedef struct {
+    int32_t status, candidate;  /* pdhg_status; returned candidate */
+    int64_t iters;
+    int32_t restarts, n_snap;
+    double sigma_hat, eta, omega0, omega, tau, sigma;
+    double t_setup, t_iter;     /* seconds in configure / in iterate calls */
+    pdhg_kkt kkt;               /* of the iterate get_iterate returns */
+} pdhg_info;
+
+typedef struct {
+    double level;               /* tolerance that fired */
+    int64_t iter;               /* iteration of the emitting evaluation */
+    double maxresid;            /* maxresid of the emitted iterate */
+    int32_t candidate, pad_;
+    double t_wall;              /* seconds since the solve started */
+} pdhg_snapshot_info;
+
+typedef struct {
+    double outer_eps;           /* stop when FP64 maxresid <= outer_eps (1e-8) */
+    double inner_eps;           /* inner (correction LP) eps_rel (1e-4) */
+    int32_t max_rounds;         /* refinement rounds after round 0 (8) */
+    int32_t cap_log2;           /* scale growth cap per round, 2^cap (10) */
+    int64_t max_inner_iters;    /* per inner solve (1e7) */
+} pdhg_refine_params;
+
+typedef struct {
+    int32_t status, rounds;
+    int64_t inner_iters;        /* summed over rounds */
+    double t_total;             /* seconds */
+    pdhg_kkt kkt;               /* FP64 KKT of the final iterate */
+} pdhg_refine_info;
+
+/* Per-kernel timing record (HIP events around each launch, when enabled). */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} pdhg_kernel_time;
+
+/* ---- host-only calls (no GPU needed) ---------------------------------- */
+
+/* Fill *p with the defaults listed above (precision FP64, eps_rel 1e-6,
+ * no snapshot levels, max_iters 2^62, use_graph 1). */
+int pdhg_params_default(pdhg_params *p);
+int pdhg_refine_params_default(pdhg_refine_params *p);
+
+/* Algorithm 1's targets (Section 3.1): eps_cross / 10^j for every j with a
+ * value above eps_rel, followed by eps_rel itself.  Writes at most cap
+ * values to out and returns how many, or a negative error. */
+int pdhg_alg1_levels(double eps_cross, double eps_rel, double *out, int cap);
+
+/* Check one CSR matrix with `rows` rows over `cols` columns: rp[0] = 0,
+ * rp[rows] = nnz, non-decreasing, 0 <= ci < cols, strictly increasing inside
+ * each row, nnz < 2^31.  Returns PDHG_OK or PDHG_E_CSR with a message in msg
+ * (msg may be NULL). */
+int pdhg_validate_csr(int64_t rows, int64_t cols, int64_t nnz,
+                      const int64_t *rp, const int32_t *ci, char *msg,
+                      int msg_len);
+
+/* Check that (at_rp, at_ci, at_v) is exactly the transpose of
+ * (a_rp, a_ci, a_v), values compared bitwise.  If perm is not NULL, write
+ * perm[p] = position in A^T's arrays of A's nonzero p.  Returns PDHG_OK,
+ * PDHG_E_CSR or PDHG_E_TRANSPOSE. */
+int pdhg_check_transpose(int64_t m, int64_t n, int64_t nnz,
+                         const int64_t *a_rp, const int32_t *a_ci,
+                         const double *a_v, const int64_t *at_rp,
+                         const int32_t *at_ci, const double *at_v,
+                         int64_t *perm, char *msg, int msg_len);
+
+/* ---- context lifecycle ------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * to launch on (for example torch.cuda.current_stream().cuda_stream) or NULL
+ * for a stream the context creates (default priority). */
+int pdhg_create(int device, void *hip_stream, pdhg_ctx **out);
+void pdhg_destroy(pdhg_ctx *ctx);
+/* Last error message of this context; valid until the next call on it. */
+const char *pdhg_last_error(const pdhg_ctx *ctx);
+
+/* ---- problem data ------------------------------------------------------ */
+
+/* Load CSR A (m x n) and its explicit transpose CSR A^T (n x m), b (m),
+ * c (n) and optional lower bounds lb (n; NULL = 0).  Validates both CSRs and
+ * the transpose relation (PDHG_E_CSR / PDHG_E_TRANSPOSE), then builds the
+ * row-length bins of both matrices.  Replaces any earlier problem. */
+int pdhg_load(pdhg_ctx *ctx, int64_t m, int64_t n, int64_t nnz,
+              const int64_t *a_rp, const int32_t *a_ci, const double *a_v,
+              const int64_t *at_rp, const int32_t *at_ci, const double *at_v,
+              const double *b, const double *c, const double *lb, int mem);
+
+/* Replace A's values (nnz, in A's CSR order); A^T follows through the load
+ * permutation.  The scaling factors of the last configure are kept (frozen)
+ * and re-applied; call pdhg_configure to recompute them. */
+int pdhg_set_values(pdhg_ctx *ctx, const double *a_v, int mem);
+/* Replace b (m) and c (n) (either may be NULL to keep it); frozen scaling. */
+int pdhg_set_rhs_obj(pdhg_ctx *ctx, const double *b, const double *c, int mem);
+
+/* ---- solve ------------------------------------------------------------- */
+
+/* Copy the parameters and snapshot levels, compute the Ruiz factors D_r, D_c
+ * (ruiz_passes passes), the scaled data A~ = D_r A D_c, b~ = D_r b,
+ * c~ = D_c c, l~ = l / D_c, the power-iteration estimate sigma_hat of
+ * ||A~||_2, the step size eta, the primal weight omega and tau = eta / omega,
+ * sigma = eta * omega, and reset the iterate to zero and the status to
+ * RUNNING.  Required before pdhg_iterate. */
+int pdhg_configure(pdhg_ctx *ctx, const pdhg_params *p);
+
+/* Warm start from unscaled x (n) and y (m) (either may be NULL = zero);
+ * resets the averages, the restart state and the status. */
+int pdhg_set_iterate(pdhg_ctx *ctx, const double *x, const double *y, int mem);
+
+/* Run up to max_iters more iterations (the parameter max_iters bounds the
+ * total).  One iteration is the fused primal step
+ *   x <- max(l~, x - tau (c~ - A~^T y))
+ * followed by the extrapolated dual step
+ *   y <- y + sigma (b~ - (2 A~ x_new - A~ x_old)),
+ * and the uniform averages since the last restart.  Every eval_every
+ * iterations (and once before the first) the current and averaged iterates
+ * are evaluated in FP64; a snapshot is emitted for each not-yet-emitted
+ * level >= the better candidate's maxresid (Algorithm 1's test), the solve
+ * stops when it is <= eps_rel, and otherwise the adaptive restart rule runs.
+ * Returns when the status leaves RUNNING or the iterations are done; *status
+ * receives the pdhg_status. */
+int pdhg_iterate(pdhg_ctx *ctx, int64_t max_iters, int *status);
+
+/* Ask a running pdhg_iterate / pdhg_solve_refined to stop at its next
+ * evaluation check with PDHG_CANCELLED.  Thread-safe and idempotent. */
+int pdhg_cancel(pdhg_ctx *ctx);
+
+/* Counters, step sizes and the KKT of the current iterate. */
+int pdhg_get_info(pdhg_ctx *ctx, pdhg_info *out);
+
+/* FP64 relative KKT (Section 2) of: which = 0 current iterate, 1 average
+ * (valid after at least one iteration since the last restart). */
+int pdhg_residuals(pdhg_ctx *ctx, int which, pdhg_kkt *out);
+
+/* Unscaled current iterate: x (n), y (m), z = max(0, c - A^T y) (n).  Any
+ * pointer may be NULL. */
+int pdhg_get_iterate(pdhg_ctx *ctx, double *x, double *y, double *z, int mem);
+
+/* Ruiz factors of the last configure: dr (m), dc (n). */
+int pdhg_get_scaling(pdhg_ctx *ctx, double *dr, double *dc, int mem);
+
+/* Evaluation log: up to cap records of 8 doubles (iteration, maxresid of
+ * current and average, KKT_omega of current and average, restarted flag,
+ * restart candidate, omega after the evaluation).  *count gets the total. */
+int pdhg_eval_log(pdhg_ctx *ctx, double *out, int cap, int *count);
+
+/* ---- snapshots (Algorithm 1's crossover starting points) --------------- */
+
+int pdhg_snapshot_count(pdhg_ctx *ctx, int *count);
+/* Copy snapshot idx (0-based, in emission order): info plus unscaled
+ * x (n), y (m), z (n); any pointer may be NULL. */
+int pdhg_snapshot(pdhg_ctx *ctx, int idx, pdhg_snapshot_info *info,
+                  double *x, double *y, double *z, int mem);
+/* Register cb, called on a library thread once a snapshot's host copy is
+ * complete, with the snapshot index; cb must not call into the context. */
+int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
+                               void (*cb)(void *user, int idx,
+                                          const pdhg_snapshot_info *info),
+                               void *user);
+
+/* ---- FP32 bulk iteration with FP64 refinement --------------------------- */
+
+/* Iterative refinement: round 0 solves the LP with the bulk iteration in
+ * FP32; each later round computes FP64 residuals r_P = b - Ax,
+ * d = c - A^T y, power-of-two scales Delta_P, Delta_D, solves the correction
+ * LP  min (Delta_D d)^T xh  s.t.  A xh = Delta_P r_P,  xh >= -Delta_P x
+ * with FP32 bulk iterations and FP64 evaluations, and updates in FP64
+ * x <- max(0, x + xh / Delta_P), y <- y + yh / Delta_D, until the FP64
+ * maxresid <= outer_eps.  Uses the parameters of the last configure (its
+ * precision field is ignored).  The refined iterate becomes the context's
+ * current iterate. */
+int pdhg_solve_refined(pdhg_ctx *ctx, const pdhg_refine_params *rp,
+                       pdhg_refine_info *info);
+
+/* ---- unrolled steps and their adjoint ------------------------------------ */
+
+/* Run K plain PDHG steps (no restarts, no averaging) on the configured,
+ * scaled problem with fixed tau, sigma, from unscaled (x0, y0) (NULL: zero),
+ * in `precision`; write unscaled x_K (n).  Stores (x, y, A~x) every
+ * ckpt_every steps in a new tape (*tape; free with pdhg_tape_free). */
+int pdhg_unrolled_forward(pdhg_ctx *ctx, int K, int ckpt_every,
+                          int precision, double tau, double sigma,
+                          const double *x0, const double *y0, double *xK,
+                          int mem, pdhg_tape **tape);
+/* Reverse pass for the loss gradient gxK = dL/dx_K (n, unscaled): writes
+ * dL/dc (n), dL/db (m) and dL/dA.values (nnz, A's CSR order), with the
+ * scaling factors held fixed.  Segments between checkpoints are recomputed
+ * with the forward kernels, which are deterministic, so the result does not
+ * depend on ckpt_every.  The projection's subgradient is 0 at a tie. */
+int pdhg_unrolled_backward(pdhg_tape *tape, const double *gxK, double *gc,
+                           double *gb, double *gAval, int mem);
+void pdhg_tape_free(pdhg_tape *tape);
+
+/* ---- kernels for checking and measurement ------------------------------ */
+
+/* One binned SpMV on the device: which = 0: out (m) = A in (n);
+ * which = 1: out (n) = A^T in (m).  scaled = 1 uses A~, 0 the loaded A.
+ * precision selects the FP64 or the FP32 kernel (FP32 rounds `in` and the
+ * values to float and accumulates in float; out is widened to double). */
+int pdhg_spmv(pdhg_ctx *ctx, int which, int scaled, int precision,
+              const double *in, double *out, int mem);
+
+/* Row-bin tuning: key "split_threshold" (nnz above which a row is split over
+ * several workgroups), "split_chunk" (nnz per split part).  Takes effect at
+ * the next pdhg_load. */
+int pdhg_set_tuning(pdhg_ctx *ctx, const char *key, int64_t value);
+/* Row-block statistics of matrix which (0 = A, 1 = A^T): counts of blocks
+ * by kind {multi-row, single-row, split parts} in out[0..2]. */
+int pdhg_bin_stats(pdhg_ctx *ctx, int which, int64_t *out3);
+
+/* Enable (1) or disable (0) HIP-event timing of every iteration-kernel
+ * launch (batches then run without graphs).  pdhg_kernel_times fills up to
+ * cap records and sets *count; reset clears the records. */
+int pdhg_profile(pdhg_ctx *ctx, int enable);
+int pdhg_kernel_times(pdhg_ctx *ctx, pdhg_kernel_time *out, int cap,
+                      int *count, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHG_H */

@@ -530,6 +530,10 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
                         }
                         memcpy(xl, xs, (size_t)n * sizeof(double));
                         memcpy(yl, ys, (size_t)m * sizeof(double));
+                        /* averages start afresh: the first one after the
+                           restart is exactly the first new iterate */
+                        memset(xbar, 0, (size_t)n * sizeof(double));
+                        memset(ybar, 0, (size_t)m * sizeof(double));
                         t = 0;
                         K_last = kkt_w(S, omega);
                         K_prev = INFINITY;

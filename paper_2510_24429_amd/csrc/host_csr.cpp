@@ -1,0 +1,241 @@
+// host_csr.cpp -- host-only logic of the library: parameter defaults,
+// Algorithm 1's level schedule, CSR validation, the transpose check and the
+// row-length binning of a CSR matrix into workgroup row blocks.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+
+#include "internal.h"
+
+namespace {
+
+void put_msg(char *msg, int len, const char *text) {
+    if (msg && len > 0) {
+        std::snprintf(msg, (size_t)len, "%s", text);
+    }
+}
+
+}  // namespace
+
+extern "C" int pdhg_params_default(pdhg_params *p) {
+    if (!p) return PDHG_E_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->precision = PDHG_FP64;
+    p->ruiz_passes = 10;
+    p->power_iters = 100;
+    p->eval_every = 64;
+    p->literal_snapshots = 0;
+    p->n_levels = 0;
+    p->levels = nullptr;
+    p->eps_rel = 1e-6;
+    p->eta = 0.0;
+    p->omega0 = 0.0;
+    p->eta_factor = 0.9;
+    p->beta_suff = 0.2;
+    p->beta_nec = 0.8;
+    p->beta_art = 0.36;
+    p->omega_theta = 0.5;
+    p->max_iters = (int64_t)1 << 62;
+    p->time_limit_s = 3600.0;
+    p->use_graph = 1;
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_refine_params_default(pdhg_refine_params *p) {
+    if (!p) return PDHG_E_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->outer_eps = 1e-8;
+    p->inner_eps = 1e-4;
+    p->max_rounds = 8;
+    p->cap_log2 = 10;
+    p->max_inner_iters = 10000000;
+    return PDHG_OK;
+}
+
+// Algorithm 1 (Section 3.1) lowers its target tenfold after every launch,
+// starting at eps_cross, and stops PDHG at eps_rel.  The levels are formed
+// as eps_cross / 10^j so that rounding cannot leave a level a hair above
+// eps_rel (repeated multiplication by 0.1 does).
+extern "C" int pdhg_alg1_levels(double eps_cross, double eps_rel, double *out,
+                                int cap) {
+    if (!out || cap < 1 || !(eps_cross > 0.0) || !(eps_rel > 0.0))
+        return PDHG_E_ARG;
+    int k = 0;
+    double p10 = 1.0;
+    for (int j = 0; j < 64 && k < cap; ++j) {
+        double lev = eps_cross / p10;
+        p10 *= 10.0;
+        if (lev <= eps_rel * (1.0 + 1e-9)) break;
+        out[k++] = lev;
+    }
+    if (k < cap) out[k++] = eps_rel;
+    return k;
+}
+
+extern "C" int pdhg_validate_csr(int64_t rows, int64_t cols, int64_t nnz,
+                                 const int64_t *rp, const int32_t *ci,
+                                 char *msg, int msg_len) {
+    char buf[256];
+    if (rows < 1 || cols < 1) {
+        put_msg(msg, msg_len, "matrix must have at least one row and column");
+        return PDHG_E_CSR;
+    }
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) {
+        put_msg(msg, msg_len, "nnz must be in [0, 2^31)");
+        return PDHG_E_CSR;
+    }
+    if (cols >= ((int64_t)1 << 31) || rows >= ((int64_t)1 << 31)) {
+        put_msg(msg, msg_len, "dimensions must be below 2^31");
+        return PDHG_E_CSR;
+    }
+    if (!rp || (nnz > 0 && !ci)) {
+        put_msg(msg, msg_len, "null CSR array");
+        return PDHG_E_CSR;
+    }
+    if (rp[0] != 0 || rp[rows] != nnz) {
+        std::snprintf(buf, sizeof buf,
+                      "row pointers must start at 0 and end at nnz=%lld "
+                      "(got %lld..%lld)",
+                      (long long)nnz, (long long)rp[0], (long long)rp[rows]);
+        put_msg(msg, msg_len, buf);
+        return PDHG_E_CSR;
+    }
+    for (int64_t i = 0; i < rows; ++i) {
+        if (rp[i + 1] < rp[i]) {
+            std::snprintf(buf, sizeof buf, "row pointers decrease at row %lld",
+                          (long long)i);
+            put_msg(msg, msg_len, buf);
+            return PDHG_E_CSR;
+        }
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (ci[p] < 0 || ci[p] >= cols) {
+                std::snprintf(buf, sizeof buf,
+                              "column index %d out of range in row %lld",
+                              ci[p], (long long)i);
+                put_msg(msg, msg_len, buf);
+                return PDHG_E_CSR;
+            }
+            if (p > rp[i] && ci[p] <= ci[p - 1]) {
+                std::snprintf(buf, sizeof buf,
+                              "column indices not strictly increasing in "
+                              "row %lld",
+                              (long long)i);
+                put_msg(msg, msg_len, buf);
+                return PDHG_E_CSR;
+            }
+        }
+    }
+    return PDHG_OK;
+}
+
+// A^T's row j lists the rows i of A's column j in increasing order.  Walking
+// A row by row and appending each (i, j) to a cursor per column therefore
+// visits A^T's entries in storage order, which gives the permutation and
+// the check in one O(nnz) pass.
+extern "C" int pdhg_check_transpose(int64_t m, int64_t n, int64_t nnz,
+                                    const int64_t *a_rp, const int32_t *a_ci,
+                                    const double *a_v, const int64_t *at_rp,
+                                    const int32_t *at_ci, const double *at_v,
+                                    int64_t *perm, char *msg, int msg_len) {
+    int rc = pdhg_validate_csr(m, n, nnz, a_rp, a_ci, msg, msg_len);
+    if (rc != PDHG_OK) return rc;
+    rc = pdhg_validate_csr(n, m, nnz, at_rp, at_ci, msg, msg_len);
+    if (rc != PDHG_OK) return rc;
+    if (nnz > 0 && (!a_v || !at_v)) {
+        put_msg(msg, msg_len, "null value array");
+        return PDHG_E_ARG;
+    }
+    std::vector<int64_t> cur(at_rp, at_rp + n);
+    char buf[256];
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t p = a_rp[i]; p < a_rp[i + 1]; ++p) {
+            int32_t j = a_ci[p];
+            int64_t q = cur[j]++;
+            if (q >= at_rp[j + 1] || at_ci[q] != (int32_t)i ||
+                std::memcmp(&at_v[q], &a_v[p], sizeof(double)) != 0) {
+                std::snprintf(buf, sizeof buf,
+                              "A^T differs from the transpose of A at "
+                              "A(%lld,%d)",
+                              (long long)i, j);
+                put_msg(msg, msg_len, buf);
+                return PDHG_E_TRANSPOSE;
+            }
+            if (perm) perm[p] = q;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        if (cur[j] != at_rp[j + 1]) {
+            std::snprintf(buf, sizeof buf,
+                          "A^T row %lld has entries absent from A",
+                          (long long)j);
+            put_msg(msg, msg_len, buf);
+            return PDHG_E_TRANSPOSE;
+        }
+    }
+    return PDHG_OK;
+}
+
+namespace pdhg {
+
+// Row-length bins.  Consecutive rows are packed into multi-row blocks of at
+// most `tile` nonzeros (and at most `tile` rows); a row longer than `tile`
+// gets a workgroup of its own, and a row longer than split_threshold is cut
+// into parts of split_chunk nonzeros on several workgroups.  Single-row and
+// split blocks are placed first so that the longest work starts first.
+HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
+                          int64_t split_threshold, int64_t split_chunk) {
+    HostBins hb;
+    std::vector<RowBlock> longb, multi;
+    std::vector<std::pair<int64_t, int64_t>> singles;  // (len, row)
+    int slot = 0;
+    int64_t r = 0;
+    while (r < rows) {
+        int64_t len = rp[r + 1] - rp[r];
+        if (len > tile) {
+            if (len > split_threshold) {
+                int nparts = (int)((len + split_chunk - 1) / split_chunk);
+                for (int q = 0; q < nparts; ++q)
+                    longb.push_back({(int32_t)r, (int32_t)(r + 1), q, nparts,
+                                     slot, 0, 0, 0});
+                hb.splits.push_back({(int32_t)r, nparts});
+                hb.maxparts = std::max(hb.maxparts, nparts);
+                hb.counts[2] += nparts;
+                ++slot;
+            } else {
+                singles.push_back({len, r});
+            }
+            ++r;
+            continue;
+        }
+        int64_t r1 = r, acc = 0;
+        while (r1 < rows && (r1 - r) < tile) {
+            int64_t l = rp[r1 + 1] - rp[r1];
+            if (l > tile || acc + l > tile) break;
+            acc += l;
+            ++r1;
+        }
+        multi.push_back({(int32_t)r, (int32_t)r1, 0, 1, -1, 0, 0, 0});
+        if (r1 - r == 1)
+            hb.counts[1] += 1;
+        else
+            hb.counts[0] += 1;
+        r = r1;
+    }
+    std::stable_sort(singles.begin(), singles.end(),
+                     [](const std::pair<int64_t, int64_t> &a,
+                        const std::pair<int64_t, int64_t> &b) {
+                         return a.first > b.first;
+                     });
+    hb.blocks.reserve(longb.size() + singles.size() + multi.size());
+    for (auto &b : longb) hb.blocks.push_back(b);
+    for (auto &s : singles) {
+        hb.blocks.push_back({(int32_t)s.second, (int32_t)(s.second + 1), 0, 1,
+                             -1, 0, 0, 0});
+        hb.counts[1] += 1;
+    }
+    for (auto &b : multi) hb.blocks.push_back(b);
+    return hb;
+}
+
+}  // namespace pdhg

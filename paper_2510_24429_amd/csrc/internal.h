@@ -1,0 +1,219 @@
+// internal.h -- declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pdhg.h"
+
+namespace pdhg {
+
+constexpr int kWG = 256;          // threads per workgroup (4 wave64s)
+constexpr int kTile64 = 1024;     // nonzeros staged per multi-row block, FP64
+constexpr int kTile32 = 2048;     // same, FP32 (same LDS bytes)
+constexpr int kMaxLevels = 32;
+constexpr int kRedBlocks = 512;   // blocks per side of the KKT reduction
+
+// One workgroup's share of a CSR SpMV.  Rows [r0, r1) of one matrix:
+//  - several rows (r1 - r0 > 1): their nonzeros (<= tile) are streamed
+//    through LDS and summed by groups of lanes per row;
+//  - one row (r1 - r0 == 1, nparts == 1): all 256 lanes stride the row and
+//    reduce across the workgroup;
+//  - one row split over nparts workgroups: part `part` writes a partial sum
+//    to slot `slot`; a fix-up pass adds the parts in order.
+struct RowBlock {
+    int32_t r0, r1, part, nparts, slot, pad0, pad1, pad2;
+};
+
+struct SplitRow {
+    int32_t row, nparts;
+};
+
+struct HostBins {
+    std::vector<RowBlock> blocks;
+    std::vector<SplitRow> splits;
+    int maxparts = 1;
+    int64_t counts[3] = {0, 0, 0};   // multi-row, single-row, split parts
+};
+
+HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
+                          int64_t split_threshold, int64_t split_chunk);
+
+// Matrix resident on the device: CSR with int32 row pointers.
+struct DevCsr {
+    int64_t rows = 0, cols = 0, nnz = 0;
+    int32_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    double *v_orig = nullptr;   // loaded values
+    double *v64 = nullptr;      // scaled values (D_r A D_c), FP64
+    float *v32 = nullptr;       // scaled values rounded to FP32
+    // bins for the FP64 tile and the FP32 tile
+    RowBlock *blk64 = nullptr;
+    int nblk64 = 0;
+    RowBlock *blk32 = nullptr;
+    int nblk32 = 0;
+    SplitRow *split64 = nullptr, *split32 = nullptr;
+    int nsplit64 = 0, nsplit32 = 0, maxparts64 = 1, maxparts32 = 1;
+    double *part64 = nullptr;   // split partial sums
+    float *part32 = nullptr;
+    double *part64_f32blk = nullptr;  // FP64 sums over the FP32 bins
+    int64_t counts64[3] = {0, 0, 0};
+};
+
+// Control state of a solve, resident on the device and written only by the
+// single-workgroup control kernel (and by the host between solves).
+enum { Q_RP2, Q_RPMAX, Q_SRP2, Q_BY, Q_DY2, Q_RD2, Q_RDMAX, Q_SRD2, Q_CX,
+       Q_LZ, Q_DX2, Q_NQ };
+enum { S_RELP, S_RELD, S_RELG, S_MAXR, S_POBJ, S_DOBJ, S_NRP, S_NRD,
+       S_RPINF, S_RDINF, S_SP2, S_SD2, S_SG, S_DX2, S_DY2, S_FIN, S_NS };
+
+struct State {
+    double tau, sigma, omega, eta;
+    double K_last, K_prev;
+    double nb, nc;                  // ||b||_2, ||c||_2 of the unscaled data
+    double eps_rel, beta_suff, beta_nec, beta_art, omega_theta;
+    double pad_d;
+    long long k;                    // iterations done
+    long long t_base;               // iterations since the last restart
+    int status;
+    int copy_pending;               // 1: restart / final copy to apply
+    int copy_avg;                   // candidate copied into the current iterate
+    int set_last;                   // 1: restart point <- current afterwards
+    int restarts;
+    int next_level, n_levels, literal;
+    int snap_count;
+    int snap_first, snap_n, snap_cand;
+    int returned_cand;
+    int n_log, log_cap;
+    int last_ncand;
+    double levels[kMaxLevels];
+    double stats[2][S_NS];
+    double snap_level[kMaxLevels];
+    long long snap_iter[kMaxLevels];
+    double snap_mr[kMaxLevels];
+    int snap_cand_of[kMaxLevels];
+};
+
+// Vectors of one precision for the bulk iteration.
+template <typename T>
+struct Iter {
+    T *x = nullptr, *y = nullptr, *xbar = nullptr, *ybar = nullptr;
+    T *xl = nullptr, *yl = nullptr;       // last restart point
+    T *ax = nullptr;                      // A~ x of the current iterate
+    T *cs = nullptr, *bs = nullptr, *ls = nullptr;   // scaled data in T
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------
+
+// out = M in  (M = A~ / A / A~32 chosen by the caller through `vals`)
+void spmv_f64(const DevCsr &M, const double *vals, const double *in,
+              double *out, hipStream_t s);
+void spmv_f64_in32(const DevCsr &M, const double *vals, const float *in,
+                   double *out, hipStream_t s);
+void spmv_f32(const DevCsr &M, const float *in, float *out, hipStream_t s);
+
+template <typename T>
+void launch_primal(const DevCsr &At, const Iter<T> &v, bool has_l,
+                   bool avg, const State *st, int off, hipStream_t s);
+template <typename T>
+void launch_dual(const DevCsr &A, const Iter<T> &v, bool avg,
+                 const State *st, int off, hipStream_t s);
+
+void launch_kkt_reduce(int ncand, const void *x0, const void *y0,
+                       const void *x1, const void *y1, bool f32,
+                       const double *ax0, const double *aty0,
+                       const double *ax1, const double *aty1,
+                       const void *xl, const void *yl, const double *bs,
+                       const double *cs, const double *ls, const double *dr,
+                       const double *dc, int64_t m, int64_t n,
+                       double *partial, hipStream_t s);
+void launch_control(State *st, const double *partial, int ncand, int batch,
+                    int initial, double *log, hipStream_t s);
+void launch_advance(State *st, int batch, hipStream_t s);
+void launch_set_status(State *st, int status, hipStream_t s);
+void launch_restart_apply(State *st, bool f32, void *x, void *y, void *ax,
+                          void *xbar, void *ybar, const double *ax_avg,
+                          void *xl, void *yl, int64_t m, int64_t n,
+                          hipStream_t s);
+void launch_snapshot_pack(const State *st, bool f32, const void *x0,
+                          const void *y0, const void *x1, const void *y1,
+                          const double *aty0, const double *aty1,
+                          const double *cs, const double *dr, const double *dc,
+                          double *slots, int64_t m, int64_t n, hipStream_t s);
+
+// Ruiz: rho_r = max over row r of M of |(D_r,i a_ij) D_c,j| for the entry's
+// (i, j) in A.  d_row scales M's rows and d_col its columns; transposed = 1
+// when M is A^T (the first factor is then d_col).  The update divides d by
+// sqrt(rho) (a zero maximum counts as 1).
+void launch_ruiz_rowmax(const DevCsr &M, const double *d_row,
+                        const double *d_col, int transposed, double *rho,
+                        hipStream_t s);
+void launch_ruiz_update(double *d, const double *rho, int64_t k,
+                        hipStream_t s);
+// Entries of the rows of A scaled by fixed factors:
+// out[p] = (rs[row] * v[p]) * cs[col]; out32 (optional) gets the FP32 copy.
+void launch_scale_values(const DevCsr &M, const double *v, const double *rs,
+                         const double *cs, double *out, float *out32,
+                         hipStream_t s);
+
+// Deterministic FP64 reductions: partial sums of squares / dot products by
+// blocks, then a fixed-order finish in one workgroup.
+void launch_dot(const double *a, const double *b, int64_t k, double *partial,
+                double *result, hipStream_t s);
+void launch_scale_vec(double *dst, const double *src, const double *factor,
+                      int64_t k, int mode, hipStream_t s);
+void launch_fill(double *p, double v, int64_t k, hipStream_t s);
+void launch_fill32(float *p, float v, int64_t k, hipStream_t s);
+void launch_to_f32(float *dst, const double *src, int64_t k, hipStream_t s);
+void launch_to_f64(double *dst, const float *src, int64_t k, hipStream_t s);
+// elementwise: out = a * b (mode 0), a / b (mode 1), a * b with b a scalar
+// pointer (mode 2)
+void launch_ew(double *out, const double *a, const double *b, int64_t k,
+               int mode, hipStream_t s);
+void launch_unscale_xyz(const double *xs, const double *ys,
+                        const double *aty, const double *cs, const double *dr,
+                        const double *dc, double *x, double *y, double *z,
+                        int64_t m, int64_t n, hipStream_t s);
+void launch_unscale_xyz32(const float *xs, const float *ys,
+                          const double *aty, const double *cs,
+                          const double *dr, const double *dc, double *x,
+                          double *y, double *z, int64_t m, int64_t n,
+                          hipStream_t s);
+void launch_permute(double *dst, const double *src, const int32_t *perm,
+                    int64_t k, hipStream_t s);
+
+// Refinement (FP64): residual data of the correction LP and its update.
+void launch_refine_rhs(const double *bs, const double *ax, const double *cs,
+                       const double *aty, const double *xs, double DP,
+                       double DD, double *bh, double *ch, double *lh,
+                       int64_t m, int64_t n, hipStream_t s);
+void launch_refine_delta(const double *bs, const double *ax, const double *cs,
+                         const double *aty, const double *xs,
+                         const double *dr, const double *dc, int64_t m,
+                         int64_t n, double *partial, double *out2,
+                         hipStream_t s);
+void launch_refine_update(double *xs, double *ys, const float *xh,
+                          const float *yh, double DP, double DD, int64_t m,
+                          int64_t n, hipStream_t s);
+void launch_norm_unscaled(const double *vs, const double *d, int64_t k,
+                          double *partial, double *result, hipStream_t s);
+
+// Adjoint kernels (template over T = float/double).
+template <typename T>
+void launch_adj_dual_bwd(const DevCsr &At, const T *gy, const T *gx_in,
+                         const T *x1, const T *ls, bool has_l, T *gx_out,
+                         T *gv, T *gc, double tau, double sigma,
+                         hipStream_t s);
+template <typename T>
+void launch_adj_primal_bwd(const DevCsr &A, const T *gv, const T *gy_in,
+                           T *gy_out, T *gb, double tau, double sigma,
+                           hipStream_t s);
+template <typename T>
+void launch_adj_gA(const DevCsr &A, const int32_t *rowidx, const T *y0,
+                   const T *gy1, const T *gv, const T *x0, const T *x1,
+                   T *gA, double tau, double sigma, hipStream_t s);
+
+}  // namespace pdhg

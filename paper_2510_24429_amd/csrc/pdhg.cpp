@@ -1,0 +1,1690 @@
+// pdhg.cpp -- host side of libpdhg.so: the C ABI declared in include/pdhg.h.
+//
+// The context owns every device buffer.  Problem data live on the device in
+// both FP64 and FP32; the iterate lives in the precision of the bulk
+// iteration.  The host only launches kernels and reads back, once per
+// evaluation, the small control state that the device-side control kernel
+// writes (status, snapshot levels fired, restart counters).
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+using namespace pdhg;
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct DevError {
+    int code;
+    std::string msg;
+};
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        std::string m = std::string(what) + ": " + hipGetErrorString(e);
+        throw DevError{e == hipErrorOutOfMemory ? PDHG_E_OOM : PDHG_E_DEVICE, m};
+    }
+}
+
+#define HIPC(call) hip_check((call), #call)
+
+template <typename T>
+T *dmalloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void *p = nullptr;
+    hip_check(hipMalloc(&p, (size_t)count * sizeof(T)), "hipMalloc");
+    return (T *)p;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+struct ProfRec {
+    int kind;  // 0 primal, 1 dual
+    hipEvent_t a, b;
+};
+
+struct SnapMeta {
+    pdhg_snapshot_info info;
+    int slot;
+};
+
+struct CbItem {
+    int idx;
+    hipEvent_t ev;
+};
+
+}  // namespace
+
+struct pdhg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr, copy_stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    // problem
+    bool loaded = false, configured = false;
+    int64_t m = 0, n = 0, nnz = 0;
+    DevCsr A, At;
+    int32_t *perm = nullptr;    // A position -> A^T position
+    int32_t *rowidx = nullptr;  // row of each of A's nonzeros
+    double *b_orig = nullptr, *c_orig = nullptr, *l_orig = nullptr;
+    bool has_l = false;
+    int64_t split_threshold = (int64_t)1 << 20;
+    int64_t split_chunk = (int64_t)1 << 16;
+
+    // scaling and scaled data
+    double *dr = nullptr, *dc = nullptr;
+    double *bs = nullptr, *cs = nullptr, *ls = nullptr;       // FP64
+    float *bs32 = nullptr, *cs32 = nullptr, *ls32 = nullptr;  // FP32
+    // refinement correction data
+    double *bh = nullptr, *ch = nullptr, *lh = nullptr;
+    float *bh32 = nullptr, *ch32 = nullptr, *lh32 = nullptr;
+    double *xo = nullptr, *yo = nullptr;  // outer FP64 iterate (scaled)
+
+    // active problem of the current solve
+    const double *act_bs = nullptr, *act_cs = nullptr, *act_ls = nullptr;
+    bool act_has_l = false;
+
+    Iter<double> v64;
+    Iter<float> v32;
+    int prec = PDHG_FP64;
+
+    // evaluation temporaries
+    double *aty_cur = nullptr, *aty_avg = nullptr, *ax_avg = nullptr,
+           *ax_cur = nullptr;
+    double *partial = nullptr, *scal = nullptr, *rho = nullptr, *kap = nullptr;
+    double *log = nullptr;
+    int log_cap = 4096;
+    double *slots = nullptr;
+    int n_slots = 0;
+
+    State *st = nullptr;       // device
+    State *st_host = nullptr;  // pinned
+    State st_init;
+
+    pdhg_params params;
+    std::vector<double> levels;
+    double sigma_hat = 0, eta = 0, omega0 = 0;
+    double nb = 0, nc = 0;
+
+    // host bookkeeping of a solve
+    bool initial_done = false;
+    int64_t k_host = 0;
+    int status = PDHG_RUNNING;
+    double t_setup = 0, t_iter = 0, t_start = 0;
+    std::atomic<int> cancel_flag{0};
+    std::vector<SnapMeta> snaps;
+
+    // callback thread
+    void (*cb)(void *, int, const pdhg_snapshot_info *) = nullptr;
+    void *cb_user = nullptr;
+    std::thread cb_thread;
+    std::mutex cb_mu;
+    std::condition_variable cb_cv;
+    std::deque<CbItem> cb_queue;
+    bool cb_stop = false;
+    std::vector<double *> host_snap;
+
+    // graphs: one per (precision, eval_every, active pointers)
+    hipGraphExec_t graph = nullptr;
+    std::vector<const void *> graph_key;
+
+    // profiling
+    bool profile = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t prof_launch[2] = {0, 0};
+    double prof_ms[2] = {0, 0};
+};
+
+struct pdhg_tape {
+    pdhg_ctx *ctx = nullptr;
+    int K = 0, ck = 0, prec = PDHG_FP64, nseg = 0;
+    double tau = 0, sigma = 0;
+    void *ckx = nullptr, *cky = nullptr, *ckax = nullptr;
+    State *st = nullptr;
+};
+
+namespace {
+
+int fail(pdhg_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define API_BEGIN(ctx)                               \
+    if (!(ctx)) return PDHG_E_ARG;                   \
+    (ctx)->err.clear();                              \
+    try {                                            \
+        hip_check(hipSetDevice((ctx)->device), "hipSetDevice");
+#define API_END(ctx)                                 \
+    }                                                \
+    catch (const DevError &e) {                      \
+        return fail((ctx), e.code, e.msg);           \
+    }                                                \
+    catch (const std::bad_alloc &) {                 \
+        return fail((ctx), PDHG_E_OOM, "host allocation failed"); \
+    }                                                \
+    catch (...) {                                    \
+        return fail((ctx), PDHG_E_DEVICE, "unexpected exception"); \
+    }
+
+// Copy `count` elements into a device buffer from host or device memory.
+template <typename T>
+void copy_in(pdhg_ctx *c, T *dst, const T *src, int64_t count, int mem) {
+    if (count <= 0) return;
+    hip_check(hipMemcpyAsync(dst, src, (size_t)count * sizeof(T),
+                             mem == PDHG_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                    : hipMemcpyHostToDevice,
+                             c->stream),
+              "hipMemcpyAsync(in)");
+}
+
+template <typename T>
+void copy_out(pdhg_ctx *c, T *dst, const T *src, int64_t count, int mem) {
+    if (count <= 0 || !dst) return;
+    hip_check(hipMemcpyAsync(dst, src, (size_t)count * sizeof(T),
+                             mem == PDHG_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                    : hipMemcpyDeviceToHost,
+                             c->stream),
+              "hipMemcpyAsync(out)");
+}
+
+void sync(pdhg_ctx *c) { HIPC(hipStreamSynchronize(c->stream)); }
+
+// A caller array given by pointer and `mem`, staged to the host when needed.
+template <typename T>
+std::vector<T> to_host(pdhg_ctx *c, const T *p, int64_t count, int mem) {
+    std::vector<T> h((size_t)(count > 0 ? count : 0));
+    if (count <= 0) return h;
+    if (mem == PDHG_MEM_DEVICE) {
+        HIPC(hipMemcpyAsync(h.data(), p, (size_t)count * sizeof(T),
+                            hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+    } else {
+        std::memcpy(h.data(), p, (size_t)count * sizeof(T));
+    }
+    return h;
+}
+
+void free_csr(DevCsr &M) {
+    dfree(M.rp);
+    dfree(M.ci);
+    dfree(M.v_orig);
+    dfree(M.v64);
+    dfree(M.v32);
+    dfree(M.blk64);
+    dfree(M.blk32);
+    dfree(M.split64);
+    dfree(M.split32);
+    dfree(M.part64);
+    dfree(M.part32);
+    M = DevCsr();
+}
+
+template <typename T>
+void free_iter(Iter<T> &v) {
+    dfree(v.x);
+    dfree(v.y);
+    dfree(v.xbar);
+    dfree(v.ybar);
+    dfree(v.xl);
+    dfree(v.yl);
+    dfree(v.ax);
+}
+
+void invalidate_graph(pdhg_ctx *c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_key.clear();
+}
+
+void free_problem(pdhg_ctx *c) {
+    invalidate_graph(c);
+    free_csr(c->A);
+    free_csr(c->At);
+    dfree(c->perm);
+    dfree(c->rowidx);
+    dfree(c->b_orig);
+    dfree(c->c_orig);
+    dfree(c->l_orig);
+    dfree(c->dr);
+    dfree(c->dc);
+    dfree(c->bs);
+    dfree(c->cs);
+    dfree(c->ls);
+    dfree(c->bs32);
+    dfree(c->cs32);
+    dfree(c->ls32);
+    dfree(c->bh);
+    dfree(c->ch);
+    dfree(c->lh);
+    dfree(c->bh32);
+    dfree(c->ch32);
+    dfree(c->lh32);
+    dfree(c->xo);
+    dfree(c->yo);
+    free_iter(c->v64);
+    free_iter(c->v32);
+    dfree(c->aty_cur);
+    dfree(c->aty_avg);
+    dfree(c->ax_avg);
+    dfree(c->ax_cur);
+    dfree(c->partial);
+    dfree(c->scal);
+    dfree(c->rho);
+    dfree(c->kap);
+    dfree(c->log);
+    dfree(c->slots);
+    c->n_slots = 0;
+    for (double *h : c->host_snap)
+        if (h) (void)hipHostFree(h);
+    c->host_snap.clear();
+    c->loaded = c->configured = false;
+}
+
+// Upload one CSR (int64 row pointers on the host) and build both bin sets.
+void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
+                int64_t nnz, const std::vector<int64_t> &rp,
+                const std::vector<int32_t> &ci, const std::vector<double> &v) {
+    M.rows = rows;
+    M.cols = cols;
+    M.nnz = nnz;
+    std::vector<int32_t> rp32((size_t)rows + 1);
+    for (int64_t i = 0; i <= rows; ++i) rp32[i] = (int32_t)rp[i];
+    M.rp = dmalloc<int32_t>(rows + 1);
+    M.ci = dmalloc<int32_t>(nnz);
+    M.v_orig = dmalloc<double>(nnz);
+    M.v64 = dmalloc<double>(nnz);
+    M.v32 = dmalloc<float>(nnz);
+    HIPC(hipMemcpy(M.rp, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (nnz > 0) {
+        HIPC(hipMemcpy(M.ci, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(M.v_orig, v.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HostBins b64 = build_row_blocks(rows, rp.data(), kTile64, c->split_threshold, c->split_chunk);
+    HostBins b32 = build_row_blocks(rows, rp.data(), kTile32, c->split_threshold, c->split_chunk);
+    M.nblk64 = (int)b64.blocks.size();
+    M.nblk32 = (int)b32.blocks.size();
+    M.blk64 = dmalloc<RowBlock>(M.nblk64);
+    M.blk32 = dmalloc<RowBlock>(M.nblk32);
+    if (M.nblk64) HIPC(hipMemcpy(M.blk64, b64.blocks.data(), M.nblk64 * sizeof(RowBlock), hipMemcpyHostToDevice));
+    if (M.nblk32) HIPC(hipMemcpy(M.blk32, b32.blocks.data(), M.nblk32 * sizeof(RowBlock), hipMemcpyHostToDevice));
+    M.nsplit64 = (int)b64.splits.size();
+    M.nsplit32 = (int)b32.splits.size();
+    M.maxparts64 = b64.maxparts;
+    M.maxparts32 = b32.maxparts;
+    M.split64 = dmalloc<SplitRow>(M.nsplit64);
+    M.split32 = dmalloc<SplitRow>(M.nsplit32);
+    if (M.nsplit64) HIPC(hipMemcpy(M.split64, b64.splits.data(), M.nsplit64 * sizeof(SplitRow), hipMemcpyHostToDevice));
+    if (M.nsplit32) HIPC(hipMemcpy(M.split32, b32.splits.data(), M.nsplit32 * sizeof(SplitRow), hipMemcpyHostToDevice));
+    M.part64 = dmalloc<double>((int64_t)M.nsplit64 * M.maxparts64);
+    M.part32 = dmalloc<float>((int64_t)M.nsplit32 * M.maxparts32);
+    for (int q = 0; q < 3; ++q) M.counts64[q] = b64.counts[q];
+}
+
+template <typename T>
+void alloc_iter(Iter<T> &v, int64_t m, int64_t n) {
+    if (v.x) return;
+    v.x = dmalloc<T>(n);
+    v.xbar = dmalloc<T>(n);
+    v.xl = dmalloc<T>(n);
+    v.y = dmalloc<T>(m);
+    v.ybar = dmalloc<T>(m);
+    v.yl = dmalloc<T>(m);
+    v.ax = dmalloc<T>(m);
+}
+
+template <typename T>
+void zero_iter(pdhg_ctx *c, Iter<T> &v) {
+    HIPC(hipMemsetAsync(v.x, 0, c->n * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.xbar, 0, c->n * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.xl, 0, c->n * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.y, 0, c->m * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.ybar, 0, c->m * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.yl, 0, c->m * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.ax, 0, c->m * sizeof(T), c->stream));
+}
+
+double read_scalar(pdhg_ctx *c, const double *dptr) {
+    double h = 0;
+    HIPC(hipMemcpyAsync(&h, dptr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return h;
+}
+
+double dev_norm(pdhg_ctx *c, const double *v, int64_t k) {
+    launch_dot(v, v, k, c->partial, c->scal, c->stream);
+    return std::sqrt(read_scalar(c, c->scal));
+}
+
+// Scaled values of both CSRs from A's loaded values and the factors.
+void apply_scaling(pdhg_ctx *c) {
+    launch_scale_values(c->A, c->A.v_orig, c->dr, c->dc, c->A.v64, c->A.v32, c->stream);
+    launch_permute(c->At.v64, c->A.v64, c->perm, c->nnz, c->stream);
+    launch_to_f32(c->At.v32, c->At.v64, c->nnz, c->stream);
+}
+
+void apply_rhs_scaling(pdhg_ctx *c) {
+    launch_ew(c->bs, c->dr, c->b_orig, c->m, 0, c->stream);
+    launch_ew(c->cs, c->dc, c->c_orig, c->n, 0, c->stream);
+    if (c->has_l) launch_ew(c->ls, c->l_orig, c->dc, c->n, 1, c->stream);
+    launch_to_f32(c->bs32, c->bs, c->m, c->stream);
+    launch_to_f32(c->cs32, c->cs, c->n, c->stream);
+    if (c->has_l) launch_to_f32(c->ls32, c->ls, c->n, c->stream);
+    c->nb = dev_norm(c, c->b_orig, c->m);
+    c->nc = dev_norm(c, c->c_orig, c->n);
+}
+
+void ruiz(pdhg_ctx *c, int passes) {
+    launch_fill(c->dr, 1.0, c->m, c->stream);
+    launch_fill(c->dc, 1.0, c->n, c->stream);
+    for (int p = 0; p < passes; ++p) {
+        // row maxima of A and of A^T (the column maxima of A), both from the
+        // factors of the previous pass, then both updates
+        launch_ruiz_rowmax(c->A, c->dr, c->dc, 0, c->rho, c->stream);
+        launch_ruiz_rowmax(c->At, c->dc, c->dr, 1, c->kap, c->stream);
+        launch_ruiz_update(c->dr, c->rho, c->m, c->stream);
+        launch_ruiz_update(c->dc, c->kap, c->n, c->stream);
+    }
+}
+
+// Power iteration for sigma_hat ~ ||A~||_2: v0 = 1/sqrt(n) ones, `iters`
+// steps of w = A~^T A~ v, v = w / ||w||, then sqrt(||A~^T A~ v||).
+double power_iteration(pdhg_ctx *c, int iters) {
+    double *v = c->aty_avg, *u = c->ax_avg, *w = c->aty_cur;
+    launch_fill(v, 1.0 / std::sqrt((double)c->n), c->n, c->stream);
+    for (int it = 0; it <= iters; ++it) {
+        spmv_f64(c->A, c->A.v64, v, u, c->stream);
+        spmv_f64(c->At, c->At.v64, u, w, c->stream);
+        launch_dot(w, w, c->n, c->partial, c->scal, c->stream);
+        if (it < iters) launch_scale_vec(v, w, c->scal, c->n, 0, c->stream);
+    }
+    double nw2 = read_scalar(c, c->scal);
+    double s = std::sqrt(std::sqrt(nw2));
+    return (s > 0.0 && std::isfinite(s)) ? s : 1.0;
+}
+
+void write_state(pdhg_ctx *c, const State &s) {
+    HIPC(hipMemcpyAsync(c->st, &s, sizeof(State), hipMemcpyHostToDevice, c->stream));
+    sync(c);
+}
+
+void read_state(pdhg_ctx *c) {
+    HIPC(hipMemcpyAsync(c->st_host, c->st, sizeof(State), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+// Initial control state for a fresh solve of the active problem.
+State fresh_state(pdhg_ctx *c, double omega, double nb, double nc) {
+    State s;
+    std::memset(&s, 0, sizeof s);
+    s.eta = c->eta;
+    s.omega = omega;
+    s.tau = c->eta / omega;
+    s.sigma = c->eta * omega;
+    s.K_last = INFINITY;
+    s.K_prev = INFINITY;
+    s.nb = nb;
+    s.nc = nc;
+    s.eps_rel = c->params.eps_rel;
+    s.beta_suff = c->params.beta_suff;
+    s.beta_nec = c->params.beta_nec;
+    s.beta_art = c->params.beta_art;
+    s.omega_theta = c->params.omega_theta;
+    s.status = PDHG_RUNNING;
+    s.n_levels = (int)c->levels.size();
+    s.literal = c->params.literal_snapshots;
+    s.log_cap = c->log_cap;
+    for (size_t i = 0; i < c->levels.size(); ++i) s.levels[i] = c->levels[i];
+    return s;
+}
+
+void reset_solve(pdhg_ctx *c) {
+    c->initial_done = false;
+    c->k_host = 0;
+    c->status = PDHG_RUNNING;
+    c->t_iter = 0;
+    c->snaps.clear();
+    c->cancel_flag.store(0);
+}
+
+bool f32(pdhg_ctx *c) { return c->prec == PDHG_FP32; }
+
+void *cur_x(pdhg_ctx *c) { return f32(c) ? (void *)c->v32.x : (void *)c->v64.x; }
+void *cur_y(pdhg_ctx *c) { return f32(c) ? (void *)c->v32.y : (void *)c->v64.y; }
+
+// A~ x and A~^T y (FP64) of the current iterate into ax_cur / aty_cur.
+void current_products(pdhg_ctx *c, bool need_ax) {
+    if (f32(c)) {
+        if (need_ax) spmv_f64_in32(c->A, c->A.v64, c->v32.x, c->ax_cur, c->stream);
+        spmv_f64_in32(c->At, c->At.v64, c->v32.y, c->aty_cur, c->stream);
+    } else {
+        if (need_ax) spmv_f64(c->A, c->A.v64, c->v64.x, c->ax_cur, c->stream);
+        spmv_f64(c->At, c->At.v64, c->v64.y, c->aty_cur, c->stream);
+    }
+}
+
+// The evaluation sequence after a batch of `batch` iterations (initial: the
+// k = 0 check of the starting point, current iterate only).
+void enqueue_eval(pdhg_ctx *c, int batch, bool initial) {
+    const bool h = f32(c);
+    const int ncand = initial ? 1 : 2;
+    // FP64 products of the candidates
+    if (h) {
+        spmv_f64_in32(c->A, c->A.v64, c->v32.x, c->ax_cur, c->stream);
+        spmv_f64_in32(c->At, c->At.v64, c->v32.y, c->aty_cur, c->stream);
+        if (!initial) {
+            spmv_f64_in32(c->A, c->A.v64, c->v32.xbar, c->ax_avg, c->stream);
+            spmv_f64_in32(c->At, c->At.v64, c->v32.ybar, c->aty_avg, c->stream);
+        }
+    } else {
+        spmv_f64(c->At, c->At.v64, c->v64.y, c->aty_cur, c->stream);
+        if (!initial) {
+            spmv_f64(c->A, c->A.v64, c->v64.xbar, c->ax_avg, c->stream);
+            spmv_f64(c->At, c->At.v64, c->v64.ybar, c->aty_avg, c->stream);
+        }
+    }
+    const double *axc = h ? c->ax_cur : c->v64.ax;
+    const void *x0 = h ? (void *)c->v32.x : (void *)c->v64.x;
+    const void *y0 = h ? (void *)c->v32.y : (void *)c->v64.y;
+    const void *x1 = h ? (void *)c->v32.xbar : (void *)c->v64.xbar;
+    const void *y1 = h ? (void *)c->v32.ybar : (void *)c->v64.ybar;
+    const void *xl = h ? (void *)c->v32.xl : (void *)c->v64.xl;
+    const void *yl = h ? (void *)c->v32.yl : (void *)c->v64.yl;
+    launch_kkt_reduce(ncand, x0, y0, x1, y1, h, axc, c->aty_cur, c->ax_avg,
+                      c->aty_avg, xl, yl, c->act_bs, c->act_cs,
+                      c->act_has_l ? c->act_ls : nullptr, c->dr, c->dc, c->m,
+                      c->n, c->partial, c->stream);
+    launch_control(c->st, c->partial, ncand, batch, initial ? 1 : 0, c->log,
+                   c->stream);
+    if (c->n_slots > 0)
+        launch_snapshot_pack(c->st, h, x0, y0, x1, y1, c->aty_cur, c->aty_avg,
+                             c->act_cs, c->dr, c->dc, c->slots, c->m, c->n,
+                             c->stream);
+    if (h)
+        launch_restart_apply(c->st, true, c->v32.x, c->v32.y, c->v32.ax,
+                             c->v32.xbar, c->v32.ybar, c->ax_avg, c->v32.xl,
+                             c->v32.yl, c->m, c->n, c->stream);
+    else
+        launch_restart_apply(c->st, false, c->v64.x, c->v64.y, c->v64.ax,
+                             c->v64.xbar, c->v64.ybar, c->ax_avg, c->v64.xl,
+                             c->v64.yl, c->m, c->n, c->stream);
+    if (h) spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
+}
+
+hipEvent_t pool_event(pdhg_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    return e;
+}
+
+void enqueue_iterations(pdhg_ctx *c, int first_off, int count) {
+    for (int off = first_off; off < first_off + count; ++off) {
+        ProfRec r0{0, nullptr, nullptr}, r1{1, nullptr, nullptr};
+        if (c->profile) {
+            r0.a = pool_event(c);
+            r0.b = pool_event(c);
+            HIPC(hipEventRecord(r0.a, c->stream));
+        }
+        if (f32(c))
+            launch_primal<float>(c->At, c->v32, c->act_has_l, true, c->st, off, c->stream);
+        else
+            launch_primal<double>(c->At, c->v64, c->act_has_l, true, c->st, off, c->stream);
+        if (c->profile) {
+            HIPC(hipEventRecord(r0.b, c->stream));
+            r1.a = pool_event(c);
+            r1.b = pool_event(c);
+            HIPC(hipEventRecord(r1.a, c->stream));
+        }
+        if (f32(c))
+            launch_dual<float>(c->A, c->v32, true, c->st, off, c->stream);
+        else
+            launch_dual<double>(c->A, c->v64, true, c->st, off, c->stream);
+        if (c->profile) {
+            HIPC(hipEventRecord(r1.b, c->stream));
+            c->prof.push_back(r0);
+            c->prof.push_back(r1);
+        }
+    }
+}
+
+void resolve_profile(pdhg_ctx *c) {
+    if (c->prof.empty()) return;
+    sync(c);
+    for (auto &r : c->prof) {
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, r.a, r.b));
+        c->prof_ms[r.kind] += ms;
+        c->prof_launch[r.kind] += 1;
+        c->ev_pool.push_back(r.a);
+        c->ev_pool.push_back(r.b);
+    }
+    c->prof.clear();
+}
+
+std::vector<const void *> current_graph_key(pdhg_ctx *c) {
+    return {(const void *)(intptr_t)c->prec, (const void *)(intptr_t)c->params.eval_every,
+            c->act_bs, c->act_cs, c->act_ls, (const void *)(intptr_t)c->act_has_l,
+            cur_x(c), (const void *)(intptr_t)c->n_slots};
+}
+
+// One full batch (eval_every iterations + evaluation) as a replayed graph.
+bool launch_batch_graph(pdhg_ctx *c) {
+    auto key = current_graph_key(c);
+    if (!c->graph || key != c->graph_key) {
+        invalidate_graph(c);
+        hipGraph_t g;
+        HIPC(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_iterations(c, 0, c->params.eval_every);
+        enqueue_eval(c, c->params.eval_every, false);
+        HIPC(hipStreamEndCapture(c->stream, &g));
+        hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph = nullptr;
+            hip_check(e, "hipGraphInstantiate");
+        }
+        c->graph_key = key;
+    }
+    HIPC(hipGraphLaunch(c->graph, c->stream));
+    return true;
+}
+
+void cb_worker(pdhg_ctx *c) {
+    for (;;) {
+        CbItem it;
+        {
+            std::unique_lock<std::mutex> lk(c->cb_mu);
+            c->cb_cv.wait(lk, [c] { return c->cb_stop || !c->cb_queue.empty(); });
+            if (c->cb_queue.empty()) return;
+            it = c->cb_queue.front();
+            c->cb_queue.pop_front();
+        }
+        (void)hipEventSynchronize(it.ev);
+        (void)hipEventDestroy(it.ev);
+        pdhg_snapshot_info info = c->snaps[it.idx].info;
+        if (c->cb) c->cb(c->cb_user, it.idx, &info);
+    }
+}
+
+// New snapshots reported by the last evaluation: record their metadata and,
+// when a callback is registered, start their host copy on the copy stream.
+void collect_snapshots(pdhg_ctx *c) {
+    const State &s = *c->st_host;
+    const int before = (int)c->snaps.size();
+    for (int i = before; i < s.snap_count; ++i) {
+        SnapMeta sm;
+        std::memset(&sm, 0, sizeof sm);
+        sm.info.level = s.snap_level[i];
+        sm.info.iter = s.snap_iter[i];
+        sm.info.maxresid = s.snap_mr[i];
+        sm.info.candidate = s.snap_cand_of[i];
+        sm.info.t_wall = now_s() - c->t_start;
+        sm.slot = s.snap_first;
+        c->snaps.push_back(sm);
+    }
+    if (!c->cb || (int)c->snaps.size() == before) return;
+    const int64_t len = 2 * c->n + c->m;
+    const int slot = c->snaps[before].slot;
+    if ((int)c->host_snap.size() < c->n_slots) c->host_snap.resize(c->n_slots, nullptr);
+    if (!c->host_snap[slot])
+        HIPC(hipHostMalloc((void **)&c->host_snap[slot], len * sizeof(double), hipHostMallocDefault));
+    hipEvent_t ready, done;
+    HIPC(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIPC(hipEventRecord(ready, c->stream));
+    HIPC(hipStreamWaitEvent(c->copy_stream, ready, 0));
+    HIPC(hipMemcpyAsync(c->host_snap[slot], c->slots + (int64_t)slot * len,
+                        len * sizeof(double), hipMemcpyDeviceToHost, c->copy_stream));
+    HIPC(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPC(hipEventRecord(done, c->copy_stream));
+    (void)hipEventDestroy(ready);
+    {
+        std::lock_guard<std::mutex> lk(c->cb_mu);
+        for (int i = before; i < (int)c->snaps.size(); ++i) {
+            hipEvent_t e = done;
+            if (i > before) {
+                HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                HIPC(hipEventRecord(e, c->copy_stream));
+            }
+            c->cb_queue.push_back({i, e});
+        }
+    }
+    c->cb_cv.notify_one();
+}
+
+// The iteration loop shared by pdhg_iterate and the refinement's inner
+// solves.  Runs until the status leaves RUNNING or `max_more` iterations.
+int run_iterations(pdhg_ctx *c, int64_t max_more, int64_t limit_total) {
+    if (!c->initial_done) {
+        c->t_start = now_s();
+        enqueue_eval(c, 0, true);
+        read_state(c);
+        c->initial_done = true;
+        c->status = c->st_host->status;
+        collect_snapshots(c);
+    }
+    const double t0 = now_s();
+    const int64_t target = std::min(c->k_host + max_more, limit_total);
+    const int N = c->params.eval_every;
+    while (c->status == PDHG_RUNNING) {
+        if (c->k_host >= limit_total) {
+            launch_set_status(c->st, PDHG_ITER_LIMIT, c->stream);
+            read_state(c);
+            c->status = c->st_host->status;
+            break;
+        }
+        if (c->k_host >= target) break;
+        const int64_t rem = target - c->k_host;
+        const int to_eval = N - (int)(c->k_host % N);
+        const int B = (int)std::min<int64_t>(rem, to_eval);
+        const bool eval = (B == to_eval);
+        if (eval && B == N && c->params.use_graph && !c->profile) {
+            launch_batch_graph(c);
+        } else {
+            enqueue_iterations(c, 0, B);
+            if (eval)
+                enqueue_eval(c, B, false);
+            else
+                launch_advance(c->st, B, c->stream);
+        }
+        c->k_host += B;
+        if (eval) {
+            read_state(c);
+            c->status = c->st_host->status;
+            c->k_host = c->st_host->k;
+            collect_snapshots(c);
+            if (c->status == PDHG_RUNNING) {
+                int stop = 0;
+                if (c->cancel_flag.load()) stop = PDHG_CANCELLED;
+                else if (c->params.time_limit_s > 0 &&
+                         now_s() - c->t_start > c->params.time_limit_s)
+                    stop = PDHG_TIME_LIMIT;
+                if (stop) {
+                    launch_set_status(c->st, stop, c->stream);
+                    read_state(c);
+                    c->status = c->st_host->status;
+                }
+            }
+            if (c->profile) resolve_profile(c);
+        }
+    }
+    if (c->profile) resolve_profile(c);
+    sync(c);
+    c->t_iter += now_s() - t0;
+    return c->status;
+}
+
+void kkt_of(pdhg_ctx *c, int which, pdhg_kkt *out);
+
+void finish_totals(pdhg_ctx *c, const double *Q, double nb, double nc,
+                   pdhg_kkt *o) {
+    o->norm_rp = std::sqrt(Q[Q_RP2]);
+    o->norm_rd = std::sqrt(Q[Q_RD2]);
+    o->rp_inf = Q[Q_RPMAX];
+    o->rd_inf = Q[Q_RDMAX];
+    o->pobj = Q[Q_CX];
+    o->dobj = Q[Q_BY] + Q[Q_LZ];
+    o->rel_p = o->norm_rp / (1.0 + nb);
+    o->rel_d = o->norm_rd / (1.0 + nc);
+    o->rel_gap = std::fabs(o->pobj - o->dobj) /
+                 (1.0 + std::fabs(o->pobj) + std::fabs(o->dobj));
+    o->maxresid = std::max(o->rel_p, std::max(o->rel_d, o->rel_gap));
+    if (!std::isfinite(o->rel_p) || !std::isfinite(o->rel_d) || !std::isfinite(o->rel_gap))
+        o->maxresid = NAN;
+    (void)c;
+}
+
+// FP64 KKT of an arbitrary scaled FP64 pair on the active problem, through
+// the same reduction kernel as the evaluations (partials then host sums in a
+// fixed order).
+void kkt_pair64(pdhg_ctx *c, const double *xs, const double *ys,
+                const double *bs, const double *cs, const double *ls,
+                double nb, double nc, pdhg_kkt *out) {
+    spmv_f64(c->A, c->A.v64, xs, c->ax_cur, c->stream);
+    spmv_f64(c->At, c->At.v64, ys, c->aty_cur, c->stream);
+    launch_kkt_reduce(1, xs, ys, xs, ys, false, c->ax_cur, c->aty_cur,
+                      c->ax_cur, c->aty_cur, xs, ys, bs, cs, ls, c->dr, c->dc,
+                      c->m, c->n, c->partial, c->stream);
+    const int nbk = 2 * kRedBlocks;
+    std::vector<double> h((size_t)Q_NQ * nbk);
+    HIPC(hipMemcpyAsync(h.data(), c->partial, h.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    double Q[Q_NQ];
+    for (int q = 0; q < Q_NQ; ++q) {
+        double v = 0.0;
+        for (int b = 0; b < nbk; ++b) {
+            double p = h[(size_t)q * nbk + b];
+            v = (q == Q_RPMAX || q == Q_RDMAX) ? std::max(v, p) : v + p;
+        }
+        Q[q] = v;
+    }
+    finish_totals(c, Q, nb, nc, out);
+}
+
+void kkt_of(pdhg_ctx *c, int which, pdhg_kkt *out) {
+    // bring the candidate to FP64 scaled vectors in xo/yo scratch
+    const bool h = f32(c);
+    double *xs = c->xo, *ys = c->yo;
+    if (h) {
+        launch_to_f64(xs, which ? c->v32.xbar : c->v32.x, c->n, c->stream);
+        launch_to_f64(ys, which ? c->v32.ybar : c->v32.y, c->m, c->stream);
+    } else {
+        HIPC(hipMemcpyAsync(xs, which ? c->v64.xbar : c->v64.x, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(ys, which ? c->v64.ybar : c->v64.y, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    kkt_pair64(c, xs, ys, c->act_bs, c->act_cs, c->act_has_l ? c->act_ls : nullptr,
+               c->st_host->nb, c->st_host->nc, out);
+    out->iter = c->k_host;
+    out->candidate = which;
+}
+
+void configure_solve_state(pdhg_ctx *c) {
+    c->act_bs = c->bs;
+    c->act_cs = c->cs;
+    c->act_ls = c->ls;
+    c->act_has_l = c->has_l;
+    c->v64.bs = c->bs;
+    c->v64.cs = c->cs;
+    c->v64.ls = c->ls;
+    c->v32.bs = c->bs32;
+    c->v32.cs = c->cs32;
+    c->v32.ls = c->ls32;
+}
+
+}  // namespace
+
+// ============================================================== the C ABI
+
+extern "C" {
+
+const char *pdhg_last_error(const pdhg_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+int pdhg_create(int device, void *hip_stream, pdhg_ctx **out) {
+    if (!out) return PDHG_E_ARG;
+    *out = nullptr;
+    pdhg_ctx *c = nullptr;
+    try {
+        c = new pdhg_ctx();
+    } catch (...) {
+        return PDHG_E_OOM;
+    }
+    c->device = device;
+    try {
+        int count = 0;
+        HIPC(hipGetDeviceCount(&count));
+        if (device < 0 || device >= count) throw DevError{PDHG_E_ARG, "no such device"};
+        HIPC(hipSetDevice(device));
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            // a blocking stream: ordered after work on the null stream, so
+            // inputs written there by the caller are complete
+            HIPC(hipStreamCreate(&c->stream));
+            c->own_stream = true;
+        }
+        HIPC(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+        HIPC(hipHostMalloc((void **)&c->st_host, sizeof(State), hipHostMallocDefault));
+        std::memset(c->st_host, 0, sizeof(State));
+        c->st = dmalloc<State>(1);
+    } catch (const DevError &) {
+        pdhg_destroy(c);
+        return PDHG_E_DEVICE;
+    } catch (...) {
+        pdhg_destroy(c);
+        return PDHG_E_OOM;
+    }
+    pdhg_params_default(&c->params);
+    *out = c;
+    return PDHG_OK;
+}
+
+void pdhg_destroy(pdhg_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    if (c->cb_thread.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(c->cb_mu);
+            c->cb_stop = true;
+        }
+        c->cb_cv.notify_all();
+        c->cb_thread.join();
+    }
+    free_problem(c);
+    for (auto &r : c->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    dfree(c->st);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int pdhg_set_tuning(pdhg_ctx *c, const char *key, int64_t value) {
+    if (!c || !key) return PDHG_E_ARG;
+    if (std::strcmp(key, "split_threshold") == 0 && value >= kTile32) {
+        c->split_threshold = value;
+        return PDHG_OK;
+    }
+    if (std::strcmp(key, "split_chunk") == 0 && value >= kWG) {
+        c->split_chunk = value;
+        return PDHG_OK;
+    }
+    return fail(c, PDHG_E_ARG, "unknown tuning key or value out of range");
+}
+
+int pdhg_load(pdhg_ctx *c, int64_t m, int64_t n, int64_t nnz,
+              const int64_t *a_rp, const int32_t *a_ci, const double *a_v,
+              const int64_t *at_rp, const int32_t *at_ci, const double *at_v,
+              const double *b, const double *cvec, const double *lb,
+              int mem) {
+    API_BEGIN(c)
+    if (m < 1 || n < 1 || nnz < 0 || !a_rp || !at_rp || !b || !cvec ||
+        (mem != PDHG_MEM_HOST && mem != PDHG_MEM_DEVICE))
+        return fail(c, PDHG_E_ARG, "bad argument to pdhg_load");
+    if (nnz > 0 && (!a_ci || !a_v || !at_ci || !at_v))
+        return fail(c, PDHG_E_ARG, "null CSR array");
+    auto h_arp = to_host(c, a_rp, m + 1, mem);
+    auto h_atrp = to_host(c, at_rp, n + 1, mem);
+    auto h_aci = to_host(c, a_ci, nnz, mem);
+    auto h_atci = to_host(c, at_ci, nnz, mem);
+    auto h_av = to_host(c, a_v, nnz, mem);
+    auto h_atv = to_host(c, at_v, nnz, mem);
+    std::vector<int64_t> perm((size_t)(nnz > 0 ? nnz : 0));
+    char msg[256] = {0};
+    int rc = pdhg_check_transpose(m, n, nnz, h_arp.data(), h_aci.data(),
+                                  h_av.data(), h_atrp.data(), h_atci.data(),
+                                  h_atv.data(), perm.data(), msg, sizeof msg);
+    if (rc != PDHG_OK) return fail(c, rc, msg);
+    free_problem(c);
+    c->m = m;
+    c->n = n;
+    c->nnz = nnz;
+    upload_csr(c, c->A, m, n, nnz, h_arp, h_aci, h_av);
+    upload_csr(c, c->At, n, m, nnz, h_atrp, h_atci, h_atv);
+    std::vector<int32_t> p32((size_t)nnz), ridx((size_t)nnz);
+    for (int64_t p = 0; p < nnz; ++p) p32[p] = (int32_t)perm[p];
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = h_arp[i]; p < h_arp[i + 1]; ++p) ridx[p] = (int32_t)i;
+    c->perm = dmalloc<int32_t>(nnz);
+    c->rowidx = dmalloc<int32_t>(nnz);
+    if (nnz) {
+        HIPC(hipMemcpy(c->perm, p32.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(c->rowidx, ridx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    c->b_orig = dmalloc<double>(m);
+    c->c_orig = dmalloc<double>(n);
+    copy_in(c, c->b_orig, b, m, mem);
+    copy_in(c, c->c_orig, cvec, n, mem);
+    c->has_l = lb != nullptr;
+    if (c->has_l) {
+        c->l_orig = dmalloc<double>(n);
+        copy_in(c, c->l_orig, lb, n, mem);
+    }
+    c->dr = dmalloc<double>(m);
+    c->dc = dmalloc<double>(n);
+    c->bs = dmalloc<double>(m);
+    c->cs = dmalloc<double>(n);
+    c->ls = dmalloc<double>(n);
+    c->bs32 = dmalloc<float>(m);
+    c->cs32 = dmalloc<float>(n);
+    c->ls32 = dmalloc<float>(n);
+    c->aty_cur = dmalloc<double>(n);
+    c->aty_avg = dmalloc<double>(n);
+    c->ax_avg = dmalloc<double>(m);
+    c->ax_cur = dmalloc<double>(m);
+    c->xo = dmalloc<double>(n);
+    c->yo = dmalloc<double>(m);
+    c->rho = dmalloc<double>(m);
+    c->kap = dmalloc<double>(n);
+    c->partial = dmalloc<double>(2 * Q_NQ * 2 * kRedBlocks);
+    c->scal = dmalloc<double>(16);
+    c->log = dmalloc<double>(8 * (int64_t)c->log_cap);
+    // until configure: unit scaling so that pdhg_spmv works on A~ = A
+    launch_fill(c->dr, 1.0, m, c->stream);
+    launch_fill(c->dc, 1.0, n, c->stream);
+    apply_scaling(c);
+    sync(c);
+    c->loaded = true;
+    c->configured = false;
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_set_values(pdhg_ctx *c, const double *a_v, int mem) {
+    API_BEGIN(c)
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    if (!a_v && c->nnz) return fail(c, PDHG_E_ARG, "null values");
+    copy_in(c, c->A.v_orig, a_v, c->nnz, mem);
+    launch_permute(c->At.v_orig, c->A.v_orig, c->perm, c->nnz, c->stream);
+    apply_scaling(c);
+    sync(c);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_set_rhs_obj(pdhg_ctx *c, const double *b, const double *cv, int mem) {
+    API_BEGIN(c)
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    if (b) copy_in(c, c->b_orig, b, c->m, mem);
+    if (cv) copy_in(c, c->c_orig, cv, c->n, mem);
+    apply_rhs_scaling(c);
+    sync(c);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
+    API_BEGIN(c)
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    if (!p) return fail(c, PDHG_E_ARG, "null params");
+    if (p->eval_every < 1 || p->ruiz_passes < 0 || p->power_iters < 0 ||
+        p->n_levels < 0 || p->n_levels > kMaxLevels ||
+        (p->n_levels > 0 && !p->levels) ||
+        (p->precision != PDHG_FP64 && p->precision != PDHG_FP32) ||
+        !(p->eps_rel >= 0.0) || p->max_iters < 0)
+        return fail(c, PDHG_E_ARG, "invalid parameters");
+    for (int i = 1; i < p->n_levels; ++i)
+        if (!(p->levels[i] < p->levels[i - 1]))
+            return fail(c, PDHG_E_ARG, "snapshot levels must be strictly descending");
+    const double t0 = now_s();
+    invalidate_graph(c);
+    c->params = *p;
+    c->levels.assign(p->levels, p->levels + p->n_levels);
+    c->params.levels = nullptr;
+    c->prec = p->precision;
+    if (c->prec == PDHG_FP32)
+        alloc_iter(c->v32, c->m, c->n);
+    else
+        alloc_iter(c->v64, c->m, c->n);
+    if (c->n_slots < (int)c->levels.size()) {
+        dfree(c->slots);
+        c->n_slots = (int)c->levels.size();
+        c->slots = dmalloc<double>((int64_t)c->n_slots * (2 * c->n + c->m));
+    }
+    ruiz(c, p->ruiz_passes);
+    apply_scaling(c);
+    apply_rhs_scaling(c);
+    configure_solve_state(c);
+    c->sigma_hat = 0.0;
+    if (p->eta > 0.0) {
+        c->eta = p->eta;
+    } else {
+        c->sigma_hat = power_iteration(c, p->power_iters);
+        c->eta = p->eta_factor / c->sigma_hat;
+    }
+    const double nbs = dev_norm(c, c->bs, c->m), ncs = dev_norm(c, c->cs, c->n);
+    if (p->omega0 > 0.0)
+        c->omega0 = p->omega0;
+    else
+        c->omega0 = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
+    if (c->prec == PDHG_FP32)
+        zero_iter(c, c->v32);
+    else
+        zero_iter(c, c->v64);
+    c->st_init = fresh_state(c, c->omega0, c->nb, c->nc);
+    write_state(c, c->st_init);
+    *c->st_host = c->st_init;
+    reset_solve(c);
+    c->configured = true;
+    c->t_setup = now_s() - t0;
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_set_iterate(pdhg_ctx *c, const double *x, const double *y, int mem) {
+    API_BEGIN(c)
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    // scaled start in FP64 scratch: x~ = x / D_c, y~ = y / D_r
+    if (x) {
+        copy_in(c, c->xo, x, c->n, mem);
+        launch_ew(c->xo, c->xo, c->dc, c->n, 1, c->stream);
+    } else {
+        launch_fill(c->xo, 0.0, c->n, c->stream);
+    }
+    if (y) {
+        copy_in(c, c->yo, y, c->m, mem);
+        launch_ew(c->yo, c->yo, c->dr, c->m, 1, c->stream);
+    } else {
+        launch_fill(c->yo, 0.0, c->m, c->stream);
+    }
+    if (f32(c)) {
+        zero_iter(c, c->v32);
+        launch_to_f32(c->v32.x, c->xo, c->n, c->stream);
+        launch_to_f32(c->v32.y, c->yo, c->m, c->stream);
+        HIPC(hipMemcpyAsync(c->v32.xl, c->v32.x, c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v32.yl, c->v32.y, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
+    } else {
+        zero_iter(c, c->v64);
+        HIPC(hipMemcpyAsync(c->v64.x, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v64.y, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v64.xl, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v64.yl, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        spmv_f64(c->A, c->A.v64, c->v64.x, c->v64.ax, c->stream);
+    }
+    write_state(c, c->st_init);
+    *c->st_host = c->st_init;
+    reset_solve(c);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_iterate(pdhg_ctx *c, int64_t max_iters, int *status) {
+    API_BEGIN(c)
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    if (max_iters < 0) return fail(c, PDHG_E_ARG, "negative max_iters");
+    int s = run_iterations(c, max_iters, c->params.max_iters);
+    if (status) *status = s;
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_cancel(pdhg_ctx *c) {
+    if (!c) return PDHG_E_ARG;
+    c->cancel_flag.store(1);
+    return PDHG_OK;
+}
+
+int pdhg_get_info(pdhg_ctx *c, pdhg_info *o) {
+    API_BEGIN(c)
+    if (!o) return fail(c, PDHG_E_ARG, "null out");
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    read_state(c);
+    const State &s = *c->st_host;
+    std::memset(o, 0, sizeof *o);
+    o->status = c->status;
+    o->candidate = s.returned_cand;
+    o->iters = s.k;
+    o->restarts = s.restarts;
+    o->n_snap = (int)c->snaps.size();
+    o->sigma_hat = c->sigma_hat;
+    o->eta = c->eta;
+    o->omega0 = c->omega0;
+    o->omega = s.omega;
+    o->tau = s.tau;
+    o->sigma = s.sigma;
+    o->t_setup = c->t_setup;
+    o->t_iter = c->t_iter;
+    kkt_of(c, 0, &o->kkt);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_residuals(pdhg_ctx *c, int which, pdhg_kkt *out) {
+    API_BEGIN(c)
+    if (!out || which < 0 || which > 1) return fail(c, PDHG_E_ARG, "bad argument");
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    read_state(c);
+    kkt_of(c, which, out);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_get_iterate(pdhg_ctx *c, double *x, double *y, double *z, int mem) {
+    API_BEGIN(c)
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    current_products(c, false);
+    double *dx = c->xo, *dy = c->yo, *dz = c->aty_avg;
+    if (f32(c))
+        launch_unscale_xyz32(c->v32.x, c->v32.y, c->aty_cur, c->act_cs, c->dr,
+                             c->dc, dx, dy, dz, c->m, c->n, c->stream);
+    else
+        launch_unscale_xyz(c->v64.x, c->v64.y, c->aty_cur, c->act_cs, c->dr,
+                           c->dc, dx, dy, dz, c->m, c->n, c->stream);
+    copy_out(c, x, dx, c->n, mem);
+    copy_out(c, y, dy, c->m, mem);
+    copy_out(c, z, dz, c->n, mem);
+    sync(c);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_get_scaling(pdhg_ctx *c, double *dr, double *dc, int mem) {
+    API_BEGIN(c)
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    copy_out(c, dr, c->dr, c->m, mem);
+    copy_out(c, dc, c->dc, c->n, mem);
+    sync(c);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_eval_log(pdhg_ctx *c, double *out, int cap, int *count) {
+    API_BEGIN(c)
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    read_state(c);
+    const int nlog = c->st_host->n_log;
+    if (count) *count = nlog;
+    const int k = std::min(nlog, std::max(cap, 0));
+    if (out && k > 0) {
+        HIPC(hipMemcpyAsync(out, c->log, (size_t)k * 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+    }
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_snapshot_count(pdhg_ctx *c, int *count) {
+    if (!c || !count) return PDHG_E_ARG;
+    *count = (int)c->snaps.size();
+    return PDHG_OK;
+}
+
+int pdhg_snapshot(pdhg_ctx *c, int idx, pdhg_snapshot_info *info, double *x,
+                  double *y, double *z, int mem) {
+    API_BEGIN(c)
+    if (idx < 0 || idx >= (int)c->snaps.size())
+        return fail(c, PDHG_E_ARG, "snapshot index out of range");
+    const SnapMeta &sm = c->snaps[idx];
+    if (info) *info = sm.info;
+    const double *base = c->slots + (int64_t)sm.slot * (2 * c->n + c->m);
+    copy_out(c, x, base, c->n, mem);
+    copy_out(c, y, base + c->n, c->m, mem);
+    copy_out(c, z, base + c->n + c->m, c->n, mem);
+    sync(c);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_set_snapshot_callback(pdhg_ctx *c,
+                               void (*cb)(void *, int, const pdhg_snapshot_info *),
+                               void *user) {
+    API_BEGIN(c)
+    c->cb = cb;
+    c->cb_user = user;
+    if (cb && !c->cb_thread.joinable()) {
+        c->cb_stop = false;
+        c->cb_thread = std::thread(cb_worker, c);
+    }
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_spmv(pdhg_ctx *c, int which, int scaled, int precision,
+              const double *in, double *out, int mem) {
+    API_BEGIN(c)
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    if (which < 0 || which > 1 || !in || !out) return fail(c, PDHG_E_ARG, "bad argument");
+    const DevCsr &M = which ? c->At : c->A;
+    const int64_t nin = M.cols, nout = M.rows;
+    double *din = dmalloc<double>(nin), *dout = dmalloc<double>(nout);
+    copy_in(c, din, in, nin, mem);
+    if (precision == PDHG_FP32) {
+        float *i32 = dmalloc<float>(nin), *o32 = dmalloc<float>(nout);
+        launch_to_f32(i32, din, nin, c->stream);
+        if (!scaled) {
+            // FP32 copy of the loaded values
+            launch_to_f32(M.v32, M.v_orig, M.nnz, c->stream);
+        }
+        spmv_f32(M, i32, o32, c->stream);
+        launch_to_f64(dout, o32, nout, c->stream);
+        if (!scaled) launch_to_f32(M.v32, M.v64, M.nnz, c->stream);
+        sync(c);
+        dfree(i32);
+        dfree(o32);
+    } else {
+        spmv_f64(M, scaled ? M.v64 : M.v_orig, din, dout, c->stream);
+    }
+    copy_out(c, out, dout, nout, mem);
+    sync(c);
+    dfree(din);
+    dfree(dout);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_bin_stats(pdhg_ctx *c, int which, int64_t *out3) {
+    if (!c || !out3 || which < 0 || which > 1) return PDHG_E_ARG;
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    const DevCsr &M = which ? c->At : c->A;
+    for (int q = 0; q < 3; ++q) out3[q] = M.counts64[q];
+    return PDHG_OK;
+}
+
+int pdhg_profile(pdhg_ctx *c, int enable) {
+    API_BEGIN(c)
+    c->profile = enable != 0;
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_kernel_times(pdhg_ctx *c, pdhg_kernel_time *out, int cap, int *count,
+                      int reset) {
+    API_BEGIN(c)
+    resolve_profile(c);
+    const char *names[2] = {"primal_step", "dual_step"};
+    if (count) *count = 2;
+    for (int k = 0; k < 2 && k < cap && out; ++k) {
+        std::memset(&out[k], 0, sizeof out[k]);
+        std::snprintf(out[k].name, sizeof out[k].name, "%s", names[k]);
+        out[k].launches = c->prof_launch[k];
+        out[k].total_ms = c->prof_ms[k];
+    }
+    if (reset) {
+        c->prof_launch[0] = c->prof_launch[1] = 0;
+        c->prof_ms[0] = c->prof_ms[1] = 0;
+    }
+    return PDHG_OK;
+    API_END(c)
+}
+
+// ------------------------------------------------------------ refinement
+
+int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
+                       pdhg_refine_info *info) {
+    API_BEGIN(c)
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    pdhg_refine_params R;
+    if (rp)
+        R = *rp;
+    else
+        pdhg_refine_params_default(&R);
+    if (R.max_rounds < 0 || R.cap_log2 < 0 || R.cap_log2 > 60)
+        return fail(c, PDHG_E_ARG, "invalid refinement parameters");
+    const double t0 = now_s();
+    alloc_iter(c->v32, c->m, c->n);
+    if (!c->bh) {
+        c->bh = dmalloc<double>(c->m);
+        c->ch = dmalloc<double>(c->n);
+        c->lh = dmalloc<double>(c->n);
+        c->bh32 = dmalloc<float>(c->m);
+        c->ch32 = dmalloc<float>(c->n);
+        c->lh32 = dmalloc<float>(c->n);
+    }
+    double *xo = dmalloc<double>(c->n), *yo = dmalloc<double>(c->m);
+    launch_fill(xo, 0.0, c->n, c->stream);
+    launch_fill(yo, 0.0, c->m, c->stream);
+    const pdhg_params saved = c->params;
+    const std::vector<double> saved_levels = c->levels;
+    const int saved_slots = c->n_slots;
+    double DP = 1.0, DD = 1.0;
+    int status = PDHG_ITER_LIMIT, r = 0;
+    int64_t inner_total = 0;
+    pdhg_kkt K;
+    std::memset(&K, 0, sizeof K);
+    try {
+        c->levels.clear();
+        c->n_slots = 0;
+        c->params.eps_rel = R.inner_eps;
+        c->params.max_iters = R.max_inner_iters;
+        for (r = 0;; ++r) {
+            // outer FP64 KKT of (xo, yo) on the original problem
+            kkt_pair64(c, xo, yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);
+            if (K.maxresid <= R.outer_eps) {
+                status = PDHG_CONVERGED;
+                break;
+            }
+            if (!std::isfinite(K.maxresid)) {
+                status = PDHG_NUMERICAL;
+                break;
+            }
+            if (r > R.max_rounds) break;
+            if (c->cancel_flag.load()) {
+                status = PDHG_CANCELLED;
+                break;
+            }
+            // ax_cur = A~ xo, aty_cur = A~^T yo from kkt_pair64
+            if (r >= 1) {
+                launch_refine_delta(c->bs, c->ax_cur, c->cs, c->aty_cur, xo,
+                                    c->dr, c->dc, c->m, c->n, c->partial,
+                                    c->scal, c->stream);
+                double d2[2];
+                HIPC(hipMemcpyAsync(d2, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+                sync(c);
+                const double capP = std::ldexp(DP, R.cap_log2), capD = std::ldexp(DD, R.cap_log2);
+                auto pow2floor_inv = [](double d) {
+                    int e = 0;
+                    const double f = std::frexp(d, &e);  // d = f 2^e, f in [0.5, 1)
+                    return f == 0.5 ? std::ldexp(1.0, 1 - e) : std::ldexp(1.0, -e);
+                };
+                const double sP = d2[0] > 0.0 ? pow2floor_inv(d2[0]) : capP;
+                const double sD = d2[1] > 0.0 ? pow2floor_inv(d2[1]) : capD;
+                DP = std::min(sP, capP);
+                DD = std::min(sD, capD);
+            }
+            launch_refine_rhs(c->bs, c->ax_cur, c->cs, c->aty_cur, xo, DP, DD,
+                              c->bh, c->ch, c->lh, c->m, c->n, c->stream);
+            launch_to_f32(c->bh32, c->bh, c->m, c->stream);
+            launch_to_f32(c->ch32, c->ch, c->n, c->stream);
+            launch_to_f32(c->lh32, c->lh, c->n, c->stream);
+            launch_norm_unscaled(c->bh, c->dr, c->m, c->partial, c->scal, c->stream);
+            const double nbh = std::sqrt(read_scalar(c, c->scal));
+            launch_norm_unscaled(c->ch, c->dc, c->n, c->partial, c->scal, c->stream);
+            const double nch = std::sqrt(read_scalar(c, c->scal));
+            const double nbs = dev_norm(c, c->bh, c->m), ncs = dev_norm(c, c->ch, c->n);
+            const double om = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
+            // inner solve of the correction LP with FP32 bulk iterations
+            c->prec = PDHG_FP32;
+            c->act_bs = c->bh;
+            c->act_cs = c->ch;
+            c->act_ls = c->lh;
+            c->act_has_l = true;
+            c->v32.bs = c->bh32;
+            c->v32.cs = c->ch32;
+            c->v32.ls = c->lh32;
+            zero_iter(c, c->v32);
+            State s = fresh_state(c, om, nbh, nch);
+            write_state(c, s);
+            reset_solve(c);
+            run_iterations(c, R.max_inner_iters, R.max_inner_iters);
+            inner_total += c->k_host;
+            launch_refine_update(xo, yo, c->v32.x, c->v32.y, DP, DD, c->m, c->n, c->stream);
+        }
+    } catch (...) {
+        c->params = saved;
+        c->levels = saved_levels;
+        c->n_slots = saved_slots;
+        configure_solve_state(c);
+        dfree(xo);
+        dfree(yo);
+        throw;
+    }
+    // the refined iterate becomes the current FP64 iterate
+    c->params = saved;
+    c->levels = saved_levels;
+    c->n_slots = saved_slots;
+    configure_solve_state(c);
+    invalidate_graph(c);
+    c->prec = PDHG_FP64;
+    alloc_iter(c->v64, c->m, c->n);
+    zero_iter(c, c->v64);
+    HIPC(hipMemcpyAsync(c->v64.x, xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPC(hipMemcpyAsync(c->v64.y, yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPC(hipMemcpyAsync(c->v64.xl, xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPC(hipMemcpyAsync(c->v64.yl, yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    spmv_f64(c->A, c->A.v64, c->v64.x, c->v64.ax, c->stream);
+    State s = fresh_state(c, c->omega0, c->nb, c->nc);
+    s.status = status == PDHG_CONVERGED ? PDHG_CONVERGED : PDHG_RUNNING;
+    s.k = inner_total;
+    write_state(c, s);
+    *c->st_host = s;
+    reset_solve(c);
+    c->k_host = inner_total;
+    c->status = s.status;
+    c->initial_done = true;
+    dfree(xo);
+    dfree(yo);
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->status = status;
+        info->rounds = r;
+        info->inner_iters = inner_total;
+        info->t_total = now_s() - t0;
+        info->kkt = K;
+    }
+    return PDHG_OK;
+    API_END(c)
+}
+
+// ------------------------------------------------------------ adjoint
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+void unrolled_forward_T(pdhg_ctx *c, pdhg_tape *tp, const double *x0,
+                        const double *y0, double *xK, int mem) {
+    const int64_t m = c->m, n = c->n;
+    const int nck = tp->nseg;
+    tp->ckx = dmalloc<T>((int64_t)nck * n);
+    tp->cky = dmalloc<T>((int64_t)nck * m);
+    tp->ckax = dmalloc<T>((int64_t)nck * m);
+    Iter<T> w;
+    w.x = dmalloc<T>(n);
+    w.y = dmalloc<T>(m);
+    w.ax = dmalloc<T>(m);
+    if constexpr (sizeof(T) == 8) {
+        w.bs = c->bs; w.cs = c->cs; w.ls = c->ls;
+    } else {
+        w.bs = c->bs32; w.cs = c->cs32; w.ls = c->ls32;
+    }
+    // scaled start
+    if (x0) {
+        copy_in(c, c->xo, x0, n, mem);
+        launch_ew(c->xo, c->xo, c->dc, n, 1, c->stream);
+    } else {
+        launch_fill(c->xo, 0.0, n, c->stream);
+    }
+    if (y0) {
+        copy_in(c, c->yo, y0, m, mem);
+        launch_ew(c->yo, c->yo, c->dr, m, 1, c->stream);
+    } else {
+        launch_fill(c->yo, 0.0, m, c->stream);
+    }
+    if constexpr (sizeof(T) == 8) {
+        HIPC(hipMemcpyAsync(w.x, c->xo, n * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(w.y, c->yo, m * 8, hipMemcpyDeviceToDevice, c->stream));
+        spmv_f64(c->A, c->A.v64, w.x, w.ax, c->stream);
+    } else {
+        launch_to_f32(w.x, c->xo, n, c->stream);
+        launch_to_f32(w.y, c->yo, m, c->stream);
+        spmv_f32(c->A, w.x, w.ax, c->stream);
+    }
+    for (int k = 0; k < tp->K; ++k) {
+        if (k % tp->ck == 0) {
+            const int s = k / tp->ck;
+            HIPC(hipMemcpyAsync((T *)tp->ckx + (int64_t)s * n, w.x, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+            HIPC(hipMemcpyAsync((T *)tp->cky + (int64_t)s * m, w.y, m * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+            HIPC(hipMemcpyAsync((T *)tp->ckax + (int64_t)s * m, w.ax, m * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        }
+        launch_primal<T>(c->At, w, c->has_l, false, tp->st, 0, c->stream);
+        launch_dual<T>(c->A, w, false, tp->st, 0, c->stream);
+    }
+    // x_K unscaled
+    double *xd = c->xo;
+    if constexpr (sizeof(T) == 8)
+        HIPC(hipMemcpyAsync(xd, w.x, n * 8, hipMemcpyDeviceToDevice, c->stream));
+    else
+        launch_to_f64(xd, w.x, n, c->stream);
+    launch_ew(xd, xd, c->dc, n, 0, c->stream);
+    copy_out(c, xK, xd, n, mem);
+    sync(c);
+    dfree(w.x);
+    dfree(w.y);
+    dfree(w.ax);
+}
+
+template <typename T>
+void unrolled_backward_T(pdhg_tape *tp, const double *gxK, double *gc,
+                         double *gb, double *gA, int mem) {
+    pdhg_ctx *c = tp->ctx;
+    const int64_t m = c->m, n = c->n, nnz = c->nnz;
+    const int ck = tp->ck;
+    T *X = dmalloc<T>((int64_t)(ck + 1) * n);
+    T *Y = dmalloc<T>((int64_t)(ck + 1) * m);
+    T *axw = dmalloc<T>(m);
+    T *gx = dmalloc<T>(n), *gx2 = dmalloc<T>(n), *gv = dmalloc<T>(n);
+    T *gy = dmalloc<T>(m), *gy2 = dmalloc<T>(m);
+    T *gcs = dmalloc<T>(n), *gbs = dmalloc<T>(m), *gAs = dmalloc<T>(nnz);
+    HIPC(hipMemsetAsync(gy, 0, m * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(gcs, 0, n * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(gbs, 0, m * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(gAs, 0, nnz * sizeof(T), c->stream));
+    // dL/dx~_K = D_c dL/dx_K
+    copy_in(c, c->xo, gxK, n, mem);
+    launch_ew(c->xo, c->xo, c->dc, n, 0, c->stream);
+    if constexpr (sizeof(T) == 8)
+        HIPC(hipMemcpyAsync(gx, c->xo, n * 8, hipMemcpyDeviceToDevice, c->stream));
+    else
+        launch_to_f32(gx, c->xo, n, c->stream);
+    const T *ls = nullptr;
+    if constexpr (sizeof(T) == 8) ls = c->ls; else ls = c->ls32;
+    Iter<T> w;
+    if constexpr (sizeof(T) == 8) {
+        w.bs = c->bs; w.cs = c->cs; w.ls = c->ls;
+    } else {
+        w.bs = c->bs32; w.cs = c->cs32; w.ls = c->ls32;
+    }
+    w.ax = axw;
+    for (int seg = tp->nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * ck, s1 = std::min(tp->K, s0 + ck);
+        HIPC(hipMemcpyAsync(X, (T *)tp->ckx + (int64_t)seg * n, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(Y, (T *)tp->cky + (int64_t)seg * m, m * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(axw, (T *)tp->ckax + (int64_t)seg * m, m * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        for (int t = 0; t < s1 - s0; ++t) {
+            T *xt = X + (int64_t)t * n, *xt1 = X + (int64_t)(t + 1) * n;
+            T *yt = Y + (int64_t)t * m, *yt1 = Y + (int64_t)(t + 1) * m;
+            HIPC(hipMemcpyAsync(xt1, xt, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+            w.x = xt1;
+            w.y = yt;
+            launch_primal<T>(c->At, w, c->has_l, false, tp->st, 0, c->stream);
+            HIPC(hipMemcpyAsync(yt1, yt, m * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+            w.y = yt1;
+            launch_dual<T>(c->A, w, false, tp->st, 0, c->stream);
+        }
+        for (int k = s1 - 1; k >= s0; --k) {
+            const int t = k - s0;
+            const T *xk = X + (int64_t)t * n, *xk1 = X + (int64_t)(t + 1) * n;
+            const T *yk = Y + (int64_t)t * m;
+            launch_adj_dual_bwd<T>(c->At, gy, gx, xk1, ls, c->has_l, gx2, gv,
+                                   gcs, tp->tau, tp->sigma, c->stream);
+            launch_adj_gA<T>(c->A, c->rowidx, yk, gy, gv, xk, xk1, gAs,
+                             tp->tau, tp->sigma, c->stream);
+            launch_adj_primal_bwd<T>(c->A, gv, gy, gy2, gbs, tp->tau,
+                                     tp->sigma, c->stream);
+            std::swap(gx, gx2);
+            std::swap(gy, gy2);
+        }
+    }
+    // unscale: dL/dc = D_c dL/dc~, dL/db = D_r dL/db~,
+    // dL/dA_ij = (D_r,i dL/dA~_ij) D_c,j
+    double *g64 = dmalloc<double>(nnz > n ? (nnz > m ? nnz : m) : (n > m ? n : m));
+    double *out = dmalloc<double>(nnz > n ? (nnz > m ? nnz : m) : (n > m ? n : m));
+    auto widen = [&](const T *src, int64_t k) {
+        if constexpr (sizeof(T) == 8)
+            HIPC(hipMemcpyAsync(g64, src, k * 8, hipMemcpyDeviceToDevice, c->stream));
+        else
+            launch_to_f64(g64, src, k, c->stream);
+    };
+    widen(gcs, n);
+    launch_ew(out, g64, c->dc, n, 0, c->stream);
+    copy_out(c, gc, out, n, mem);
+    sync(c);
+    widen(gbs, m);
+    launch_ew(out, g64, c->dr, m, 0, c->stream);
+    copy_out(c, gb, out, m, mem);
+    sync(c);
+    widen(gAs, nnz);
+    launch_scale_values(c->A, g64, c->dr, c->dc, out, nullptr, c->stream);
+    copy_out(c, gA, out, nnz, mem);
+    sync(c);
+    dfree(g64);
+    dfree(out);
+    dfree(X);
+    dfree(Y);
+    dfree(axw);
+    dfree(gx);
+    dfree(gx2);
+    dfree(gv);
+    dfree(gy);
+    dfree(gy2);
+    dfree(gcs);
+    dfree(gbs);
+    dfree(gAs);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_unrolled_forward(pdhg_ctx *c, int K, int ckpt_every, int precision,
+                          double tau, double sigma, const double *x0,
+                          const double *y0, double *xK, int mem,
+                          pdhg_tape **tape) {
+    API_BEGIN(c)
+    if (!tape || !xK || K < 1 || ckpt_every < 1 || !(tau > 0.0) || !(sigma > 0.0) ||
+        (precision != PDHG_FP64 && precision != PDHG_FP32))
+        return fail(c, PDHG_E_ARG, "bad argument to pdhg_unrolled_forward");
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    *tape = nullptr;
+    pdhg_tape *tp = new pdhg_tape();
+    tp->ctx = c;
+    tp->K = K;
+    tp->ck = std::min(ckpt_every, K);
+    tp->prec = precision;
+    tp->nseg = (K + tp->ck - 1) / tp->ck;
+    tp->tau = tau;
+    tp->sigma = sigma;
+    try {
+        tp->st = dmalloc<State>(1);
+        State s;
+        std::memset(&s, 0, sizeof s);
+        s.tau = tau;
+        s.sigma = sigma;
+        s.status = PDHG_RUNNING;
+        HIPC(hipMemcpyAsync(tp->st, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+        if (precision == PDHG_FP32)
+            unrolled_forward_T<float>(c, tp, x0, y0, xK, mem);
+        else
+            unrolled_forward_T<double>(c, tp, x0, y0, xK, mem);
+    } catch (...) {
+        pdhg_tape_free(tp);
+        throw;
+    }
+    *tape = tp;
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_unrolled_backward(pdhg_tape *tp, const double *gxK, double *gc,
+                           double *gb, double *gAval, int mem) {
+    if (!tp || !tp->ctx) return PDHG_E_ARG;
+    pdhg_ctx *c = tp->ctx;
+    API_BEGIN(c)
+    if (!gxK || !gc || !gb || !gAval) return fail(c, PDHG_E_ARG, "null argument");
+    if (tp->prec == PDHG_FP32)
+        unrolled_backward_T<float>(tp, gxK, gc, gb, gAval, mem);
+    else
+        unrolled_backward_T<double>(tp, gxK, gc, gb, gAval, mem);
+    return PDHG_OK;
+    API_END(c)
+}
+
+void pdhg_tape_free(pdhg_tape *tp) {
+    if (!tp) return;
+    if (tp->ctx) (void)hipSetDevice(tp->ctx->device);
+    if (tp->ctx && tp->ctx->stream) (void)hipStreamSynchronize(tp->ctx->stream);
+    if (tp->ckx) (void)hipFree(tp->ckx);
+    if (tp->cky) (void)hipFree(tp->cky);
+    if (tp->ckax) (void)hipFree(tp->ckax);
+    if (tp->st) (void)hipFree(tp->st);
+    delete tp;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host-only calls (defaults, Algorithm 1 schedule, CSR
+validation, transpose check, row binning statistics) behave.  No GPU needed."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_24429_amd import _lib as L
+from paper_2510_24429_amd import lpgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdhg.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdhg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    names = header_functions()
+    assert len(names) >= 30
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # compile a probe against the header and compare every field offset with
+    # the ctypes mirror
+    structs = {"pdhg_params": L.Params, "pdhg_kkt": L.KKT, "pdhg_info": L.Info,
+               "pdhg_snapshot_info": L.SnapInfo,
+               "pdhg_refine_params": L.RefineParams,
+               "pdhg_refine_info": L.RefineInfo,
+               "pdhg_kernel_time": L.KernelTime}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdhg.h"',
+             'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    for line in out:
+        if not line:
+            continue
+        cname, field, val = line.split()
+        py = structs[cname]
+        if field == "size":
+            assert C.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, field).offset == int(val), (cname, field)
+
+
+def test_param_defaults():
+    p, _ = L.default_params()
+    assert (p.ruiz_passes, p.power_iters, p.eval_every) == (10, 100, 64)
+    assert p.eps_rel == 1e-6 and p.eta_factor == 0.9
+    assert (p.beta_suff, p.beta_nec, p.beta_art, p.omega_theta) == (0.2, 0.8, 0.36, 0.5)
+
+
+def _golden():
+    out = []
+    with open(os.path.join(ROOT, "tests", "golden", "alg1_schedule.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                lhs, rhs = line.split(":")
+                out.append((*map(float, lhs.split()), [float(t) for t in rhs.split()]))
+    return out
+
+
+@pytest.mark.parametrize("ec,er,expect", _golden())
+def test_alg1_levels_match_paper(ec, er, expect):
+    got = L.alg1_levels(ec, er)
+    assert len(got) == len(expect)
+    assert np.allclose(got, expect, rtol=1e-15, atol=0)
+
+
+def _validate(rows, cols, rp, ci):
+    rp = np.asarray(rp, dtype=np.int64)
+    ci = np.asarray(ci, dtype=np.int32)
+    msg = C.create_string_buffer(256)
+    rc = L.lib().pdhg_validate_csr(rows, cols, int(rp[-1]),
+                                   rp.ctypes.data_as(C.c_void_p),
+                                   ci.ctypes.data_as(C.c_void_p), msg, 256)
+    return rc, msg.value.decode()
+
+
+def test_validate_csr():
+    assert _validate(2, 3, [0, 2, 3], [0, 2, 1])[0] == 0
+    rc, msg = _validate(2, 3, [0, 2, 1, 3][:3], [0, 2, 1])
+    assert rc == -2
+    rc, msg = _validate(2, 3, [0, 2, 3], [0, 3, 1])
+    assert rc == -2 and "out of range" in msg
+    rc, msg = _validate(2, 3, [0, 2, 3], [2, 0, 1])
+    assert rc == -2 and "increasing" in msg
+    rc, msg = _validate(2, 3, [0, 2, 3], [1, 1, 1])
+    assert rc == -2
+    rc, msg = _validate(2, 3, [1, 2, 3], [0, 1, 2])
+    assert rc == -2
+
+
+def _check_t(lp, at_v=None, at_ci=None):
+    perm = np.zeros(lp.nnz, dtype=np.int64)
+    msg = C.create_string_buffer(256)
+    arrs = [lp.a_rp, lp.a_ci, lp.a_v, lp.at_rp,
+            lp.at_ci if at_ci is None else at_ci,
+            lp.at_v if at_v is None else at_v]
+    rc = L.lib().pdhg_check_transpose(lp.m, lp.n, lp.nnz,
+                                      *[a.ctypes.data_as(C.c_void_p) for a in arrs],
+                                      perm.ctypes.data_as(C.c_void_p), msg, 256)
+    return rc, perm, msg.value.decode()
+
+
+def test_transpose_check_and_permutation():
+    lp = lpgen.planted_powerlaw(m=300, n=2000, kmax=200, seed=3)
+    rc, perm, _ = _check_t(lp)
+    assert rc == 0
+    assert np.array_equal(perm, lp.a_perm_to_at())
+    bad = lp.at_v.copy()
+    bad[17] = np.nextafter(bad[17], np.inf)          # one ulp: bitwise check
+    rc, _, msg = _check_t(lp, at_v=bad)
+    assert rc == -3 and "transpose" in msg
+    badc = lp.at_ci.copy()
+    j = int(np.argmax(np.diff(lp.at_rp) >= 2))
+    p = lp.at_rp[j]
+    badc[p], badc[p + 1] = badc[p + 1], badc[p]     # unsorted row
+    rc, _, _ = _check_t(lp, at_ci=badc)
+    assert rc == -2
+
+
+def test_loading_without_gpu_reports_device_error():
+    # creating a context needs a GPU; on a CPU-only machine the call must fail
+    # cleanly with an error code rather than crash
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    ctx = C.c_void_p()
+    rc = L.lib().pdhg_create(0, None, C.byref(ctx))
+    assert rc < 0 and not ctx.value

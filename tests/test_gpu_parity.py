@@ -1,0 +1,288 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (through the C ABI).
+
+Bars: bitwise for the Ruiz factors and for integer-valued SpMVs; 1e-10
+relative per iteration on the iterates over the first 100 iterations; 1e-12
+absolute on the final relative KKT errors; same iteration counts, restarts
+and snapshot points.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2510_24429_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2510_24429_amd.solver import Solver as S
+    return S
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _integer_lp(seed=0):
+    """Integer-valued CSR spanning every bin: empty rows, short rows, rows
+    between the tiles, single-workgroup rows and rows long enough to split."""
+    rng = np.random.default_rng(seed)
+    m, n = 3000, 40000
+    lens = np.concatenate([
+        np.zeros(50, dtype=np.int64),
+        rng.integers(1, 17, 2000),
+        rng.integers(17, 1025, 800),
+        np.array([1023, 1024, 1025, 2047, 2048, 2049, 4096, 4097]),
+        rng.integers(4098, 9000, 40),
+        np.array([20000, 30001, 39999]),
+    ])
+    lens = lens[:m] if lens.shape[0] >= m else np.concatenate(
+        [lens, rng.integers(0, 8, m - lens.shape[0])])
+    rng.shuffle(lens)
+    rows, cols = [], []
+    for i, L in enumerate(lens):
+        c = rng.choice(n, size=int(L), replace=False)
+        rows.append(np.full(int(L), i))
+        cols.append(c)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = rng.integers(-3, 4, rows.shape[0]).astype(np.float64)
+    vals[vals == 0] = 1.0
+    return lpgen.from_coo(m, n, rows, cols, vals, np.ones(m), np.ones(n), name="int")
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_spmv_bins_bitwise_on_integers(Solver, split):
+    lp = _integer_lp()
+    tuning = {"split_threshold": 4096, "split_chunk": 1000} if split else None
+    s = Solver.from_lp(lp, tuning=tuning)
+    st = s.bin_stats(0)
+    assert st[0] > 0 and st[1] > 0
+    if split:
+        assert st[2] > 0
+    rng = np.random.default_rng(1)
+    x = rng.integers(-5, 6, lp.n).astype(np.float64)
+    y = rng.integers(-5, 6, lp.m).astype(np.float64)
+    A = lp.dense()
+    ax = A @ x      # integers well below 2^24: exact in any order
+    aty = A.T @ y
+    assert np.array_equal(s.spmv(0, x), ax)
+    assert np.array_equal(s.spmv(1, y), aty)
+    assert np.array_equal(s.spmv(0, x, precision=1), ax)
+    assert np.array_equal(s.spmv(1, y, precision=1), aty)
+    s.close()
+
+
+def test_ruiz_factors_bitwise(Solver, oracle):
+    for lp in (lpgen.make("uniform_m500_n1k"),
+               lpgen.planted_powerlaw(m=2000, n=10000, kmax=1500, seed=7)):
+        dr, dc, _ = oracle.ruiz(lp, 10)
+        with Solver.from_lp(lp) as s:
+            s.configure(ruiz_passes=10, power_iters=5)
+            gdr, gdc = s.get_scaling()
+        assert np.array_equal(gdr, dr)
+        assert np.array_equal(gdc, dc)
+
+
+def test_power_iteration_matches(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    ref = oracle.solve(lp, eps_rel=1e-6, max_iters=0)
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-6)
+        inf = s.info()
+    assert abs(inf["sigma_hat"] - ref.info["sigma_hat"]) <= 1e-13 * ref.info["sigma_hat"]
+    assert abs(inf["omega0"] - ref.info["omega0"]) <= 1e-13 * ref.info["omega0"]
+
+
+def _trace_parity(Solver, oracle, lp, K, l=None, **kw):
+    ref = oracle.solve(lp, l=l, trace_k=K, **kw)
+    worst = 0.0
+    with Solver.from_lp(lp, lb=l) as s:
+        s.configure(**kw)
+        for k in range(K):
+            s.iterate(1)
+            x, y, _ = s.get_iterate()
+            worst = max(worst, rel(x, ref.trace_x[k]), rel(y, ref.trace_y[k]))
+    return worst
+
+
+def test_iterates_first_100_match_oracle(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8)
+    assert worst <= 1e-10, worst
+
+
+def test_iterates_match_with_eval_every_iteration(Solver, oracle):
+    # Algorithm 1 tests maxresid before every iteration: eval_every = 1
+    lp = lpgen.make("uniform_m500_n1k")
+    worst = _trace_parity(Solver, oracle, lp, 60, eps_rel=1e-8, eval_every=1)
+    assert worst <= 1e-10, worst
+
+
+def test_iterates_match_with_lower_bounds(Solver, oracle):
+    lp = lpgen.planted_uniform(m=800, n=2500, k=6, seed=12)
+    l = -np.random.default_rng(12).uniform(0.0, 0.5, lp.n)
+    worst = _trace_parity(Solver, oracle, lp, 100, l=l, eps_rel=1e-8, eval_every=16)
+    assert worst <= 1e-10, worst
+
+
+def test_iterates_match_multi_tile_ragged(Solver, oracle):
+    # several tiles per kernel, a ragged last block, short and long rows
+    lp = lpgen.planted_powerlaw(m=3000, n=20000, kmax=2500, seed=21)
+    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, eval_every=32)
+    assert worst <= 1e-10, worst
+
+
+def _solve_both(Solver, oracle, lp, levels, eps, **kw):
+    ref = oracle.solve(lp, levels=levels, eps_rel=eps, keep_snap_vectors=True, **kw)
+    s = Solver.from_lp(lp)
+    s.configure(levels=levels, eps_rel=eps, **kw)
+    st = s.solve()
+    return ref, s, st
+
+
+def test_full_solve_kkt_and_snapshots(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    levels = [1e-4, 1e-6]
+    ref, s, st = _solve_both(Solver, oracle, lp, levels, 1e-6)
+    inf = s.info()
+    assert st == 1 and ref.info["status"] == 1
+    assert inf["iters"] == ref.info["iters"]
+    assert inf["restarts"] == ref.info["restarts"]
+    for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
+        assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
+    assert abs(inf["kkt"]["pobj"] - ref.kkt["pobj"]) <= 1e-9 * (1 + abs(ref.kkt["pobj"]))
+    log = s.eval_log()
+    assert np.array_equal(log[:, 0], ref.eval_log[:, 0])
+    assert np.array_equal(log[:, 5], ref.eval_log[:, 5])          # restarts
+    assert s.snapshot_count() == len(ref.snaps) == 2
+    for i, sn in enumerate(ref.snaps):
+        info, x, y, z = s.snapshot(i)
+        assert info["level"] == sn["level"] and info["iter"] == sn["iter"]
+        assert abs(info["maxresid"] - sn["maxresid"]) <= 1e-12
+        assert rel(x, ref.snap_x[i]) <= 1e-8 and rel(y, ref.snap_y[i]) <= 1e-8
+        assert np.max(np.abs(z - ref.snap_z[i])) <= 1e-8 * (1 + np.max(np.abs(ref.snap_z[i])))
+        # the snapshot satisfies the level on the original data (CPU recompute)
+        kk = oracle.kkt(lp, x, y)
+        assert kk["maxresid"] <= sn["level"]
+    s.close()
+
+
+def test_full_solve_alg1_schedule_1e8(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    levels = oracle.alg1_levels(1e-2, 1e-8)
+    ref, s, st = _solve_both(Solver, oracle, lp, levels, 1e-8, literal_snapshots=1)
+    assert st == 1
+    got = [s.snapshot(i)[0] for i in range(s.snapshot_count())]
+    assert [g["level"] for g in got] == [r["level"] for r in ref.snaps] == levels
+    assert [g["iter"] for g in got] == [r["iter"] for r in ref.snaps]
+    inf = s.info()
+    for key in ("rel_p", "rel_d", "rel_gap"):
+        assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12
+    s.close()
+
+
+def test_graph_and_stream_paths_agree(Solver):
+    lp = lpgen.planted_uniform(m=4000, n=9000, k=5, seed=31)
+    out = []
+    for g in (0, 1):
+        with Solver.from_lp(lp) as s:
+            s.configure(eps_rel=1e-7, use_graph=g)
+            st = s.solve()
+            x, y, _ = s.get_iterate()
+            out.append((st, s.info()["iters"], x, y))
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2]) and np.array_equal(out[0][3], out[1][3])
+
+
+def test_status_iter_limit_numerical_warm_start(Solver):
+    lp = lpgen.make("uniform_m500_n1k")
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-12, max_iters=100)
+        assert s.solve() == 2
+        assert s.info()["iters"] == 100
+    b = lp.b.copy()
+    b[3] = np.nan
+    lpn = lpgen.LP(lp.m, lp.n, lp.a_rp, lp.a_ci, lp.a_v, lp.at_rp, lp.at_ci, lp.at_v, b, lp.c)
+    with Solver.from_lp(lpn) as s:
+        s.configure(eps_rel=1e-6, max_iters=1000)
+        assert s.solve() == 5
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-6, levels=[1e-4, 1e-6])
+        s.set_iterate(lp.x_star, lp.y_star)
+        assert s.solve() == 1
+        assert s.info()["iters"] == 0 and s.snapshot_count() == 2
+
+
+def test_cancel_and_time_limit(Solver):
+    lp = lpgen.planted_uniform(m=20000, n=60000, k=5, seed=4)
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-14, time_limit_s=0.5)
+        assert s.solve() == 3
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-14)
+        threading.Timer(0.3, s.cancel).start()
+        t0 = time.time()
+        assert s.solve() == 4
+        assert time.time() - t0 < 30
+
+
+def test_snapshot_callback(Solver):
+    lp = lpgen.make("uniform_m500_n1k")
+    seen = []
+    ev = threading.Event()
+
+    def cb(idx, info):
+        seen.append((idx, info["level"]))
+        if len(seen) == 3:
+            ev.set()
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-6, levels=[1e-2, 1e-4, 1e-6])
+        s.set_snapshot_callback(cb)
+        assert s.solve() == 1
+        assert ev.wait(10)
+    assert sorted(seen) == [(0, 1e-2), (1, 1e-4), (2, 1e-6)]
+
+
+def test_bad_inputs_rejected(Solver):
+    from paper_2510_24429_amd._lib import PDHGError
+    lp = lpgen.make("uniform_m500_n1k")
+    at_v = lp.at_v.copy()
+    at_v[0] += 1.0
+    with pytest.raises(PDHGError, match="TRANSPOSE"):
+        Solver(lp.m, lp.n, lp.a_rp, lp.a_ci, lp.a_v, lp.at_rp, lp.at_ci, at_v, lp.b, lp.c)
+    with Solver.from_lp(lp) as s:
+        with pytest.raises(PDHGError, match="STATE"):
+            s.iterate(1)
+        with pytest.raises(PDHGError, match="ARG"):
+            s.configure(levels=[1e-6, 1e-4])
+
+
+def test_full_size_powerlaw_parity(Solver, oracle):
+    """The benchmark workload at full size (m=200k, n=1M, nnz~9.4M): Ruiz
+    factors bitwise, and the first iterations plus one evaluation with a
+    restart against the oracle."""
+    lp = lpgen.make("powerlaw_m200k_n1m")
+    dr, dc, _ = oracle.ruiz(lp, 10)
+    K = 4
+    kw = dict(eps_rel=1e-8, eval_every=2, eta=0.5, omega0=1.3)
+    ref = oracle.solve(lp, trace_k=K, max_iters=K, **kw)
+    with Solver.from_lp(lp) as s:
+        s.configure(**kw)
+        gdr, gdc = s.get_scaling()
+        assert np.array_equal(gdr, dr) and np.array_equal(gdc, dc)
+        for k in range(K):
+            s.iterate(1)
+            x, y, _ = s.get_iterate()
+            assert rel(x, ref.trace_x[k]) <= 1e-10, k
+            assert rel(y, ref.trace_y[k]) <= 1e-10, k
+        log = s.eval_log()
+        assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
+        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0)
