@@ -56,7 +56,8 @@ class KKT(C.Structure):
 class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("candidate", C.c_int32),
                 ("iters", C.c_int64), ("restarts", C.c_int32),
-                ("n_snap", C.c_int32), ("sigma_hat", C.c_double),
+                ("n_snap", C.c_int32), ("n_log", C.c_int32),
+                ("pad_", C.c_int32), ("sigma_hat", C.c_double),
                 ("eta", C.c_double), ("omega0", C.c_double),
                 ("omega", C.c_double), ("tau", C.c_double),
                 ("sigma", C.c_double), ("t_setup", C.c_double),
@@ -205,7 +206,7 @@ def solve(lp, levels: Sequence[float] = (), l=None, x0=None, y0=None,
     slist = [dict(level=snaps[i].level, iter=snaps[i].iter,
                   maxresid=snaps[i].maxresid, candidate=snaps[i].candidate)
              for i in range(ns)]
-    nlog = int(np.count_nonzero(elog.reshape(-1, 8)[:, 0]))
+    nlog = min(info.n_log, log_cap)
     return SolveResult(
         x, y, z, idict, info.kkt.asdict(), slist,
         None if sx is None else sx.reshape(nl, n)[:ns],

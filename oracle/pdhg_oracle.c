@@ -69,6 +69,7 @@ typedef struct {
     int32_t status, candidate;  /* candidate: 0 current, 1 average */
     int64_t iters;
     int32_t restarts, n_snap;
+    int32_t n_log, pad_;
     double sigma_hat, eta, omega0, omega, tau, sigma;
     double t_setup, t_iter;
     or_kkt_t kkt;
@@ -458,6 +459,11 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
     if (status == OR_RUNNING && Sc.kkt.maxresid <= prm->eps_rel)
         status = OR_CONVERGED;
     final_kkt = Sc.kkt;
+    if (eval_log && n_log < log_cap) {
+        double *e = eval_log + 8 * (int64_t)n_log++;
+        e[0] = 0.0; e[1] = Sc.kkt.maxresid; e[2] = NAN; e[3] = K_last;
+        e[4] = INFINITY; e[5] = 0.0; e[6] = 0.0; e[7] = omega;
+    }
 
     while (status == OR_RUNNING) {
         if (k >= prm->max_iters) { status = OR_ITER_LIMIT; break; }
@@ -575,6 +581,7 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
         info->iters = k;
         info->restarts = restarts;
         info->n_snap = n_snap;
+        info->n_log = n_log;
         info->sigma_hat = sigma_hat;
         info->eta = eta;
         info->omega0 = omega0;

@@ -285,4 +285,5 @@ def test_full_size_powerlaw_parity(Solver, oracle):
             assert rel(y, ref.trace_y[k]) <= 1e-10, k
         log = s.eval_log()
         assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
-        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0)
+        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0,
+                           equal_nan=True)

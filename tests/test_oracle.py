@@ -236,7 +236,8 @@ def test_snapshots_fire_at_first_qualifying_evaluation(oracle):
     assert r.info["status"] == 1
     assert [s["level"] for s in r.snaps] == levels
     log = r.eval_log
-    best = np.minimum(log[:, 1], log[:, 2])
+    assert log[0, 0] == 0 and np.isnan(log[0, 2])     # the k = 0 check
+    best = np.fmin(log[:, 1], log[:, 2])
     for i, s in enumerate(r.snaps):
         assert s["maxresid"] <= s["level"]
         # first evaluation at which the better candidate reached the level
