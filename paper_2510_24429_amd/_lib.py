@@ -10,7 +10,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdhg.so")
+LIB_PATH = os.environ.get("PDHG_LIB") or os.path.join(HERE, "libpdhg.so")
 
 PDHG_OK = 0
 ERRORS = {-1: "PDHG_E_ARG", -2: "PDHG_E_CSR", -3: "PDHG_E_TRANSPOSE",

@@ -18,30 +18,31 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature",
           "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = OUT, defines=(),
+          bdir: str = None) -> str:
+    """Compile every source and link the shared library at `out`.
+    `defines` (e.g. ["PDHG_TILE64=1024"]) override build-time tile sizes."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = bdir or os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
-        cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = ["-x", "hip"] + DEVICE
-        else:
-            cmd[1:1] = ["-x", "hip"] + DEVICE
+        cmd = [HIPCC, *COMMON, *["-D" + d for d in defines], "-c", path,
+               "-o", obj]
+        cmd[1:1] = ["-x", "hip"] + DEVICE
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp,
            *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

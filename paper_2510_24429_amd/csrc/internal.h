@@ -12,8 +12,14 @@
 namespace pdhg {
 
 constexpr int kWG = 256;          // threads per workgroup (4 wave64s)
-constexpr int kTile64 = 1024;     // nonzeros staged per multi-row block, FP64
-constexpr int kTile32 = 2048;     // same, FP32 (same LDS bytes)
+#ifndef PDHG_TILE64
+#define PDHG_TILE64 1024
+#endif
+#ifndef PDHG_TILE32
+#define PDHG_TILE32 2048
+#endif
+constexpr int kTile64 = PDHG_TILE64;  // nonzeros staged per multi-row block, FP64
+constexpr int kTile32 = PDHG_TILE32;  // same, FP32 (same LDS bytes)
 constexpr int kMaxLevels = 32;
 constexpr int kRedBlocks = 512;   // blocks per side of the KKT reduction
 

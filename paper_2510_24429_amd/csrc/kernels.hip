@@ -60,13 +60,21 @@ __device__ __forceinline__ double block_max(double v, double *sred) {
 
 // ---------------------------------------------------------------- elements
 
+// One nonzero's contribution v[p] * x[ci[p]].  fetch() reads the streamed
+// index and value (non-temporal: they are used once), apply() gathers x and
+// multiplies; splitting the two lets a thread issue all of its index/value
+// loads, then all of its gathers, before waiting on any of them.
 template <typename MT, typename VT, typename Acc>
 struct SpmvElem {
     const int32_t *ci;
     const MT *v;
     const VT *x;
-    __device__ __forceinline__ Acc operator()(int p) const {
-        return (Acc)ntload(v + p) * (Acc)x[ntload(ci + p)];
+    __device__ __forceinline__ void fetch(int p, int &j, MT &a) const {
+        j = ntload(ci + p);
+        a = ntload(v + p);
+    }
+    __device__ __forceinline__ Acc apply(int j, MT a) const {
+        return (Acc)a * (Acc)x[j];
     }
 };
 
@@ -182,6 +190,8 @@ template <typename Acc, int TILE, class Elem, class Epi>
 __global__ __launch_bounds__(kWG) void k_rowblock(
     const RowBlock *__restrict__ blks, const int32_t *__restrict__ rp,
     Elem elem, Epi epi_in, Acc *__restrict__ part, int maxparts) {
+    constexpr int U = TILE / kWG;     // nonzeros per thread in a full tile
+    using MT = decltype(elem.v[0] + 0);
     __shared__ Acc s_prod[TILE];
     __shared__ Acc s_red[4];
     Epi epi = epi_in;
@@ -189,16 +199,34 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
     const RowBlock b = blks[blockIdx.x];
     const int tid = threadIdx.x;
     if (b.r1 - b.r0 == 1) {
+        // one row: the workgroup strides it, four loads in flight per lane
         int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
         if (b.nparts > 1) {
             const int chunk = (p1 - p0 + b.nparts - 1) / b.nparts;
             p0 = p0 + b.part * chunk;
             p1 = min(p1, p0 + chunk);
         }
-        Acc s = (Acc)0;
-#pragma unroll 4
-        for (int p = p0 + tid; p < p1; p += kWG) s += elem(p);
-        s = block_sum(s, s_red);
+        Acc s0 = (Acc)0, s1 = (Acc)0, s2 = (Acc)0, s3 = (Acc)0;
+        int p = p0 + tid;
+        for (; p + 3 * kWG < p1; p += 4 * kWG) {
+            int j0, j1, j2, j3;
+            MT a0, a1, a2, a3;
+            elem.fetch(p, j0, a0);
+            elem.fetch(p + kWG, j1, a1);
+            elem.fetch(p + 2 * kWG, j2, a2);
+            elem.fetch(p + 3 * kWG, j3, a3);
+            s0 += elem.apply(j0, a0);
+            s1 += elem.apply(j1, a1);
+            s2 += elem.apply(j2, a2);
+            s3 += elem.apply(j3, a3);
+        }
+        for (; p < p1; p += kWG) {
+            int j0;
+            MT a0;
+            elem.fetch(p, j0, a0);
+            s0 += elem.apply(j0, a0);
+        }
+        Acc s = block_sum((s0 + s1) + (s2 + s3), s_red);
         if (tid == 0) {
             if (b.nparts > 1)
                 part[b.slot * maxparts + b.part] = s;
@@ -207,9 +235,24 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
         }
         return;
     }
+    // several rows: stream their nonzeros (contiguous, <= TILE) into LDS,
+    // all index/value loads first, then all gathers
     const int p0 = rp[b.r0];
     const int nz = rp[b.r1] - p0;
-    for (int q = tid; q < nz; q += kWG) s_prod[q] = elem(p0 + q);
+    {
+        int jj[U];
+        MT aa[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = tid + u * kWG;
+            if (q < nz) elem.fetch(p0 + q, jj[u], aa[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = tid + u * kWG;
+            if (q < nz) s_prod[q] = elem.apply(jj[u], aa[u]);
+        }
+    }
     __syncthreads();
     const int R = b.r1 - b.r0;
     if (R <= kWG) {
