@@ -56,6 +56,9 @@ def main():
                     help="seconds allowed per time-to-KKT run")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of 256 MiB (reference for "
+                         "the profiler's byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -70,6 +73,12 @@ def main():
     from paper_2510_24429_amd.solver import Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     lp = lpgen.make(args.workload)
     print(f"[bench] generated {args.workload}: m={lp.m} n={lp.n} nnz={lp.nnz} "

@@ -135,7 +135,7 @@ typedef struct {
     double inner_eps;           /* inner (correction LP) eps_rel (1e-4) */
     int32_t max_rounds;         /* refinement rounds after round 0 (8) */
     int32_t cap_log2;           /* scale growth cap per round, 2^cap (10) */
-    int64_t max_inner_iters;    /* per inner solve (1e7) */
+    int64_t max_inner_iters;    /* per inner solve (200000) */
 } pdhg_refine_params;
 
 typedef struct {
@@ -288,6 +288,12 @@ int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
  * current iterate. */
 int pdhg_solve_refined(pdhg_ctx *ctx, const pdhg_refine_params *rp,
                        pdhg_refine_info *info);
+
+/* Per-round log of the last pdhg_solve_refined: up to cap records of 8
+ * doubles (round, FP64 maxresid of the outer iterate before the round,
+ * Delta_P, Delta_D, inner iterations, inner status, inner maxresid, seconds
+ * since the start); *count gets the number of records. */
+int pdhg_refine_log(pdhg_ctx *ctx, double *out, int cap, int *count);
 
 /* ---- unrolled steps and their adjoint ------------------------------------ */
 

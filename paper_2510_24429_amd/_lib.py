@@ -135,6 +135,7 @@ SIGNATURES = {
     "pdhg_set_snapshot_callback": (i32, [vp, SNAP_CB, vp]),
     "pdhg_solve_refined": (i32, [vp, C.POINTER(RefineParams),
                                  C.POINTER(RefineInfo)]),
+    "pdhg_refine_log": (i32, [vp, vp, i32, C.POINTER(i32)]),
     "pdhg_unrolled_forward": (i32, [vp, i32, i32, i32, dbl, dbl, vp, vp, vp,
                                     i32, C.POINTER(vp)]),
     "pdhg_unrolled_backward": (i32, [vp, vp, vp, vp, vp, i32]),

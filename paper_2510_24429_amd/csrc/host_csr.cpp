@@ -1,10 +1,12 @@
 // host_csr.cpp -- host-only logic of the library: parameter defaults,
 // Algorithm 1's level schedule, CSR validation, the transpose check and the
 // row-length binning of a CSR matrix into workgroup row blocks.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <algorithm>
+#include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -49,7 +51,7 @@ extern "C" int pdhg_refine_params_default(pdhg_refine_params *p) {
     p->inner_eps = 1e-4;
     p->max_rounds = 8;
     p->cap_log2 = 10;
-    p->max_inner_iters = 10000000;
+    p->max_inner_iters = 200000;
     return PDHG_OK;
 }
 
@@ -236,6 +238,92 @@ HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
     }
     for (auto &b : multi) hb.blocks.push_back(b);
     return hb;
+}
+
+// Internal relabeling: rows of A and columns of A in order of decreasing
+// length (stable).  With rows sorted, the row-length bins of both A and A^T
+// are contiguous runs; with columns sorted, the most-referenced entries of x
+// sit together, so on skewed matrices most gathers of x hit a small region
+// that stays in cache.  A' keeps each row's entries sorted by the new column
+// index; A'^T is built from A' by one pass with a cursor per column.
+Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
+                  const int32_t *a_ci, const double *a_v,
+                  const int64_t *at_rp) {
+    Relabeled R;
+    R.pr.resize((size_t)m);
+    R.pc.resize((size_t)n);
+    std::iota(R.pr.begin(), R.pr.end(), 0);
+    std::iota(R.pc.begin(), R.pc.end(), 0);
+    // a dimension is reordered only when its lengths are skewed (longest
+    // more than kSkew times the mean); otherwise its given order, which may
+    // carry locality of its own, is kept
+    auto skewed = [](const int64_t *rp, int64_t k) {
+        int64_t mx = 0;
+        for (int64_t i = 0; i < k; ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
+        return k > 0 && (double)mx > kSkew * (double)rp[k] / (double)k;
+    };
+    R.sorted_rows = skewed(a_rp, m);
+    R.sorted_cols = skewed(at_rp, n);
+    if (R.sorted_rows)
+        std::stable_sort(R.pr.begin(), R.pr.end(), [&](int32_t a, int32_t b) {
+            return a_rp[a + 1] - a_rp[a] > a_rp[b + 1] - a_rp[b];
+        });
+    if (R.sorted_cols)
+        std::stable_sort(R.pc.begin(), R.pc.end(), [&](int32_t a, int32_t b) {
+            return at_rp[a + 1] - at_rp[a] > at_rp[b + 1] - at_rp[b];
+        });
+    std::vector<int32_t> ic((size_t)n), ir((size_t)m);
+    for (int64_t j = 0; j < n; ++j) ic[R.pc[j]] = (int32_t)j;
+    for (int64_t i = 0; i < m; ++i) ir[R.pr[i]] = (int32_t)i;
+    R.a_rp.assign((size_t)m + 1, 0);
+    for (int64_t i = 0; i < m; ++i)
+        R.a_rp[i + 1] = R.a_rp[i] + (a_rp[R.pr[i] + 1] - a_rp[R.pr[i]]);
+    R.a_ci.resize((size_t)nnz);
+    R.a_v.resize((size_t)nnz);
+    R.apos.resize((size_t)nnz);
+    // rows are independent: fill them on a few host threads
+    auto fill_rows = [&](int64_t lo, int64_t hi) {
+        std::vector<std::pair<int32_t, int32_t>> tmp;
+        for (int64_t i2 = lo; i2 < hi; ++i2) {
+            const int64_t i = R.pr[i2];
+            const int64_t p0 = a_rp[i], L = a_rp[i + 1] - p0;
+            tmp.resize((size_t)L);
+            for (int64_t q = 0; q < L; ++q)
+                tmp[q] = {ic[a_ci[p0 + q]], (int32_t)(p0 + q)};
+            std::sort(tmp.begin(), tmp.end());
+            const int64_t o = R.a_rp[i2];
+            for (int64_t q = 0; q < L; ++q) {
+                R.a_ci[o + q] = tmp[q].first;
+                R.a_v[o + q] = a_v[tmp[q].second];
+                R.apos[o + q] = tmp[q].second;
+            }
+        }
+    };
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(8, nnz / 1000000));
+    if (nt == 1) {
+        fill_rows(0, m);
+    } else {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back(fill_rows, m * t / nt, m * (t + 1) / nt);
+        for (auto &t : th) t.join();
+    }
+    R.at_rp.assign((size_t)n + 1, 0);
+    for (int64_t j = 0; j < n; ++j)
+        R.at_rp[j + 1] = R.at_rp[j] + (at_rp[R.pc[j] + 1] - at_rp[R.pc[j]]);
+    R.at_ci.resize((size_t)nnz);
+    R.at_v.resize((size_t)nnz);
+    R.perm.resize((size_t)nnz);
+    std::vector<int64_t> cur(R.at_rp.begin(), R.at_rp.end() - 1);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = R.a_rp[i]; p < R.a_rp[i + 1]; ++p) {
+            const int64_t q = cur[R.a_ci[p]]++;
+            R.at_ci[q] = (int32_t)i;
+            R.at_v[q] = R.a_v[p];
+            R.perm[p] = (int32_t)q;
+        }
+    (void)ir;
+    return R;
 }
 
 }  // namespace pdhg

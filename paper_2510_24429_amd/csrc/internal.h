@@ -48,6 +48,21 @@ struct HostBins {
 HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
                           int64_t split_threshold, int64_t split_chunk);
 
+// The internal (relabeled) problem: row i' of A' is row pr[i'] of A, column
+// j' of A' is column pc[j'] of A; apos[p'] is the position in A's arrays of
+// A''s nonzero p'; perm[p'] its position in A'^T's arrays.
+constexpr double kSkew = 8.0;
+struct Relabeled {
+    bool sorted_rows = false, sorted_cols = false;
+    std::vector<int32_t> pr, pc, apos, perm;
+    std::vector<int64_t> a_rp, at_rp;
+    std::vector<int32_t> a_ci, at_ci;
+    std::vector<double> a_v, at_v;
+};
+Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
+                  const int32_t *a_ci, const double *a_v,
+                  const int64_t *at_rp);
+
 // Matrix resident on the device: CSR with int32 row pointers.
 struct DevCsr {
     int64_t rows = 0, cols = 0, nnz = 0;
@@ -148,7 +163,8 @@ void launch_snapshot_pack(const State *st, bool f32, const void *x0,
                           const void *y0, const void *x1, const void *y1,
                           const double *aty0, const double *aty1,
                           const double *cs, const double *dr, const double *dc,
-                          double *slots, int64_t m, int64_t n, hipStream_t s);
+                          const int32_t *pr, const int32_t *pc, double *slots,
+                          int64_t m, int64_t n, hipStream_t s);
 
 // Ruiz: rho_r = max over row r of M of |(D_r,i a_ij) D_c,j| for the entry's
 // (i, j) in A.  d_row scales M's rows and d_col its columns; transposed = 1
@@ -179,17 +195,24 @@ void launch_to_f64(double *dst, const float *src, int64_t k, hipStream_t s);
 // pointer (mode 2)
 void launch_ew(double *out, const double *a, const double *b, int64_t k,
                int mode, hipStream_t s);
+// Unscaled x = D_c xs, y = D_r ys, z = max(0, (cs - aty) / D_c), each
+// written at its original index (x[pc[j]], y[pr[i]], z[pc[j]]).
 void launch_unscale_xyz(const double *xs, const double *ys,
                         const double *aty, const double *cs, const double *dr,
-                        const double *dc, double *x, double *y, double *z,
-                        int64_t m, int64_t n, hipStream_t s);
+                        const double *dc, const int32_t *pr, const int32_t *pc,
+                        double *x, double *y, double *z, int64_t m, int64_t n,
+                        hipStream_t s);
 void launch_unscale_xyz32(const float *xs, const float *ys,
                           const double *aty, const double *cs,
-                          const double *dr, const double *dc, double *x,
+                          const double *dr, const double *dc,
+                          const int32_t *pr, const int32_t *pc, double *x,
                           double *y, double *z, int64_t m, int64_t n,
                           hipStream_t s);
+// dst[idx[i]] = src[i] (scatter) / dst[i] = src[idx[i]] (gather)
 void launch_permute(double *dst, const double *src, const int32_t *perm,
                     int64_t k, hipStream_t s);
+void launch_gather(double *dst, const double *src, const int32_t *idx,
+                   int64_t k, hipStream_t s);
 
 // Refinement (FP64): residual data of the correction LP and its update.
 void launch_refine_rhs(const double *bs, const double *ax, const double *cs,

@@ -740,7 +740,8 @@ template <typename T>
 __global__ __launch_bounds__(kWG) void k_snapshot_pack(
     const State *__restrict__ st, const T *x0, const T *y0, const T *x1,
     const T *y1, const double *aty0, const double *aty1, const double *cs,
-    const double *dr, const double *dc, double *slots, int64_t m, int64_t n) {
+    const double *dr, const double *dc, const int32_t *pr, const int32_t *pc,
+    double *slots, int64_t m, int64_t n) {
     if (st->snap_n == 0) return;
     const int c = st->snap_cand;
     const T *x = c ? x1 : x0;
@@ -749,12 +750,13 @@ __global__ __launch_bounds__(kWG) void k_snapshot_pack(
     double *base = slots + (int64_t)st->snap_first * (2 * n + m);
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < n; j += stride) {
-        base[j] = dc[j] * (double)x[j];
+        const int64_t o = pc[j];
+        base[o] = dc[j] * (double)x[j];
         const double d = (cs[j] - aty[j]) / dc[j];
-        base[n + m + j] = d > 0.0 ? d : 0.0;
+        base[n + m + o] = d > 0.0 ? d : 0.0;
     }
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m; i += stride)
-        base[n + i] = dr[i] * (double)y[i];
+        base[n + pr[i]] = dr[i] * (double)y[i];
 }
 
 }  // namespace
@@ -820,18 +822,19 @@ void launch_snapshot_pack(const State *st, bool f32, const void *x0,
                           const void *y0, const void *x1, const void *y1,
                           const double *aty0, const double *aty1,
                           const double *cs, const double *dr, const double *dc,
-                          double *slots, int64_t m, int64_t n, hipStream_t s) {
+                          const int32_t *pr, const int32_t *pc, double *slots,
+                          int64_t m, int64_t n, hipStream_t s) {
     const int g = grid_for(n > m ? n : m, kWG, 4096);
     if (f32)
         hipLaunchKernelGGL(k_snapshot_pack<float>, dim3(g), dim3(kWG), 0, s,
                            st, (const float *)x0, (const float *)y0,
                            (const float *)x1, (const float *)y1, aty0, aty1,
-                           cs, dr, dc, slots, m, n);
+                           cs, dr, dc, pr, pc, slots, m, n);
     else
         hipLaunchKernelGGL(k_snapshot_pack<double>, dim3(g), dim3(kWG), 0, s,
                            st, (const double *)x0, (const double *)y0,
                            (const double *)x1, (const double *)y1, aty0, aty1,
-                           cs, dr, dc, slots, m, n);
+                           cs, dr, dc, pr, pc, slots, m, n);
 }
 
 // ============================================================ Ruiz scaling
@@ -1030,19 +1033,29 @@ __global__ __launch_bounds__(kWG) void k_ew(double *out, const double *a,
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_unscale_xyz(
     const T *xs, const T *ys, const double *aty, const double *cs,
-    const double *dr, const double *dc, double *x, double *y, double *z,
-    int64_t m, int64_t n) {
+    const double *dr, const double *dc, const int32_t *pr, const int32_t *pc,
+    double *x, double *y, double *z, int64_t m, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < n; j += stride) {
-        if (x) x[j] = dc[j] * (double)xs[j];
+        const int64_t o = pc[j];
+        if (x) x[o] = dc[j] * (double)xs[j];
         if (z) {
             const double d = (cs[j] - aty[j]) / dc[j];
-            z[j] = d > 0.0 ? d : 0.0;
+            z[o] = d > 0.0 ? d : 0.0;
         }
     }
     if (y)
         for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m; i += stride)
-            y[i] = dr[i] * (double)ys[i];
+            y[pr[i]] = dr[i] * (double)ys[i];
+}
+
+__global__ __launch_bounds__(kWG) void k_gather(double *dst,
+                                                const double *src,
+                                                const int32_t *idx,
+                                                int64_t k) {
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * kWG)
+        dst[i] = src[idx[i]];
 }
 
 __global__ __launch_bounds__(kWG) void k_permute(double *dst,
@@ -1169,26 +1182,34 @@ void launch_ew(double *out, const double *a, const double *b, int64_t k,
 
 void launch_unscale_xyz(const double *xs, const double *ys, const double *aty,
                         const double *cs, const double *dr, const double *dc,
-                        double *x, double *y, double *z, int64_t m, int64_t n,
+                        const int32_t *pr, const int32_t *pc, double *x,
+                        double *y, double *z, int64_t m, int64_t n,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_unscale_xyz<double>,
                        dim3(grid_for(n > m ? n : m, kWG, 4096)), dim3(kWG), 0,
-                       s, xs, ys, aty, cs, dr, dc, x, y, z, m, n);
+                       s, xs, ys, aty, cs, dr, dc, pr, pc, x, y, z, m, n);
 }
 
 void launch_unscale_xyz32(const float *xs, const float *ys, const double *aty,
                           const double *cs, const double *dr,
-                          const double *dc, double *x, double *y, double *z,
+                          const double *dc, const int32_t *pr,
+                          const int32_t *pc, double *x, double *y, double *z,
                           int64_t m, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_unscale_xyz<float>,
                        dim3(grid_for(n > m ? n : m, kWG, 4096)), dim3(kWG), 0,
-                       s, xs, ys, aty, cs, dr, dc, x, y, z, m, n);
+                       s, xs, ys, aty, cs, dr, dc, pr, pc, x, y, z, m, n);
 }
 
 void launch_permute(double *dst, const double *src, const int32_t *perm,
                     int64_t k, hipStream_t s) {
     hipLaunchKernelGGL(k_permute, dim3(grid_for(k, kWG, 16384)), dim3(kWG), 0,
                        s, dst, src, perm, k);
+}
+
+void launch_gather(double *dst, const double *src, const int32_t *idx,
+                   int64_t k, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(k, kWG, 16384)), dim3(kWG), 0,
+                       s, dst, src, idx, k);
 }
 
 void launch_refine_rhs(const double *bs, const double *ax, const double *cs,

@@ -86,8 +86,13 @@ struct pdhg_ctx {
     bool loaded = false, configured = false;
     int64_t m = 0, n = 0, nnz = 0;
     DevCsr A, At;
-    int32_t *perm = nullptr;    // A position -> A^T position
-    int32_t *rowidx = nullptr;  // row of each of A's nonzeros
+    // internal relabeling (rows and columns by decreasing length)
+    int32_t *pr = nullptr;      // internal row -> original row of A
+    int32_t *pc = nullptr;      // internal column -> original column
+    int32_t *apos = nullptr;    // internal nonzero -> position in A's arrays
+    int32_t *perm = nullptr;    // A' position -> A'^T position
+    int32_t *rowidx = nullptr;  // row of each of A''s nonzeros
+    double *tmp_m = nullptr, *tmp_n = nullptr;  // staging for I/O
     double *b_orig = nullptr, *c_orig = nullptr, *l_orig = nullptr;
     bool has_l = false;
     int64_t split_threshold = (int64_t)1 << 20;
@@ -135,6 +140,7 @@ struct pdhg_ctx {
     double t_setup = 0, t_iter = 0, t_start = 0;
     std::atomic<int> cancel_flag{0};
     std::vector<SnapMeta> snaps;
+    std::vector<double> refine_log;   // 8 doubles per refinement round
 
     // callback thread
     void (*cb)(void *, int, const pdhg_snapshot_info *) = nullptr;
@@ -213,6 +219,23 @@ void copy_out(pdhg_ctx *c, T *dst, const T *src, int64_t count, int mem) {
 
 void sync(pdhg_ctx *c) { HIPC(hipStreamSynchronize(c->stream)); }
 
+// Caller vector in original order -> internal order (dst[i'] = src[idx[i']]).
+void vec_in(pdhg_ctx *c, double *dst, const double *src, bool rows, int mem) {
+    const int64_t k = rows ? c->m : c->n;
+    double *tmp = rows ? c->tmp_m : c->tmp_n;
+    copy_in(c, tmp, src, k, mem);
+    launch_gather(dst, tmp, rows ? c->pr : c->pc, k, c->stream);
+}
+
+// Internal vector -> caller buffer in original order.
+void vec_out(pdhg_ctx *c, double *dst, const double *src, bool rows, int mem) {
+    if (!dst) return;
+    const int64_t k = rows ? c->m : c->n;
+    double *tmp = rows ? c->tmp_m : c->tmp_n;
+    launch_permute(tmp, src, rows ? c->pr : c->pc, k, c->stream);
+    copy_out(c, dst, tmp, k, mem);
+}
+
 // A caller array given by pointer and `mem`, staged to the host when needed.
 template <typename T>
 std::vector<T> to_host(pdhg_ctx *c, const T *p, int64_t count, int mem) {
@@ -266,6 +289,11 @@ void free_problem(pdhg_ctx *c) {
     free_csr(c->At);
     dfree(c->perm);
     dfree(c->rowidx);
+    dfree(c->pr);
+    dfree(c->pc);
+    dfree(c->apos);
+    dfree(c->tmp_m);
+    dfree(c->tmp_n);
     dfree(c->b_orig);
     dfree(c->c_orig);
     dfree(c->l_orig);
@@ -521,8 +549,8 @@ void enqueue_eval(pdhg_ctx *c, int batch, bool initial) {
                    c->stream);
     if (c->n_slots > 0)
         launch_snapshot_pack(c->st, h, x0, y0, x1, y1, c->aty_cur, c->aty_avg,
-                             c->act_cs, c->dr, c->dc, c->slots, c->m, c->n,
-                             c->stream);
+                             c->act_cs, c->dr, c->dc, c->pr, c->pc, c->slots,
+                             c->m, c->n, c->stream);
     if (h)
         launch_restart_apply(c->st, true, c->v32.x, c->v32.y, c->v32.ax,
                              c->v32.xbar, c->v32.ybar, c->ax_avg, c->v32.xl,
@@ -924,36 +952,48 @@ int pdhg_load(pdhg_ctx *c, int64_t m, int64_t n, int64_t nnz,
     auto h_atci = to_host(c, at_ci, nnz, mem);
     auto h_av = to_host(c, a_v, nnz, mem);
     auto h_atv = to_host(c, at_v, nnz, mem);
-    std::vector<int64_t> perm((size_t)(nnz > 0 ? nnz : 0));
     char msg[256] = {0};
     int rc = pdhg_check_transpose(m, n, nnz, h_arp.data(), h_aci.data(),
                                   h_av.data(), h_atrp.data(), h_atci.data(),
-                                  h_atv.data(), perm.data(), msg, sizeof msg);
+                                  h_atv.data(), nullptr, msg, sizeof msg);
     if (rc != PDHG_OK) return fail(c, rc, msg);
+    std::vector<int32_t>().swap(h_atci);
+    std::vector<double>().swap(h_atv);
     free_problem(c);
     c->m = m;
     c->n = n;
     c->nnz = nnz;
-    upload_csr(c, c->A, m, n, nnz, h_arp, h_aci, h_av);
-    upload_csr(c, c->At, n, m, nnz, h_atrp, h_atci, h_atv);
-    std::vector<int32_t> p32((size_t)nnz), ridx((size_t)nnz);
-    for (int64_t p = 0; p < nnz; ++p) p32[p] = (int32_t)perm[p];
+    Relabeled R = relabel(m, n, nnz, h_arp.data(), h_aci.data(), h_av.data(),
+                          h_atrp.data());
+    std::vector<int32_t>().swap(h_aci);
+    std::vector<double>().swap(h_av);
+    upload_csr(c, c->A, m, n, nnz, R.a_rp, R.a_ci, R.a_v);
+    upload_csr(c, c->At, n, m, nnz, R.at_rp, R.at_ci, R.at_v);
+    std::vector<int32_t> ridx((size_t)nnz);
     for (int64_t i = 0; i < m; ++i)
-        for (int64_t p = h_arp[i]; p < h_arp[i + 1]; ++p) ridx[p] = (int32_t)i;
+        for (int64_t p = R.a_rp[i]; p < R.a_rp[i + 1]; ++p) ridx[p] = (int32_t)i;
     c->perm = dmalloc<int32_t>(nnz);
     c->rowidx = dmalloc<int32_t>(nnz);
+    c->apos = dmalloc<int32_t>(nnz);
+    c->pr = dmalloc<int32_t>(m);
+    c->pc = dmalloc<int32_t>(n);
     if (nnz) {
-        HIPC(hipMemcpy(c->perm, p32.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(c->perm, R.perm.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPC(hipMemcpy(c->rowidx, ridx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(c->apos, R.apos.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    HIPC(hipMemcpy(c->pr, R.pr.data(), m * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->pc, R.pc.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->tmp_m = dmalloc<double>(m);
+    c->tmp_n = dmalloc<double>(n);
     c->b_orig = dmalloc<double>(m);
     c->c_orig = dmalloc<double>(n);
-    copy_in(c, c->b_orig, b, m, mem);
-    copy_in(c, c->c_orig, cvec, n, mem);
+    vec_in(c, c->b_orig, b, true, mem);
+    vec_in(c, c->c_orig, cvec, false, mem);
     c->has_l = lb != nullptr;
     if (c->has_l) {
         c->l_orig = dmalloc<double>(n);
-        copy_in(c, c->l_orig, lb, n, mem);
+        vec_in(c, c->l_orig, lb, false, mem);
     }
     c->dr = dmalloc<double>(m);
     c->dc = dmalloc<double>(n);
@@ -989,8 +1029,12 @@ int pdhg_set_values(pdhg_ctx *c, const double *a_v, int mem) {
     API_BEGIN(c)
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
     if (!a_v && c->nnz) return fail(c, PDHG_E_ARG, "null values");
-    copy_in(c, c->A.v_orig, a_v, c->nnz, mem);
+    double *tmp = dmalloc<double>(c->nnz);
+    copy_in(c, tmp, a_v, c->nnz, mem);
+    launch_gather(c->A.v_orig, tmp, c->apos, c->nnz, c->stream);
     launch_permute(c->At.v_orig, c->A.v_orig, c->perm, c->nnz, c->stream);
+    sync(c);
+    dfree(tmp);
     apply_scaling(c);
     sync(c);
     return PDHG_OK;
@@ -1000,8 +1044,8 @@ int pdhg_set_values(pdhg_ctx *c, const double *a_v, int mem) {
 int pdhg_set_rhs_obj(pdhg_ctx *c, const double *b, const double *cv, int mem) {
     API_BEGIN(c)
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
-    if (b) copy_in(c, c->b_orig, b, c->m, mem);
-    if (cv) copy_in(c, c->c_orig, cv, c->n, mem);
+    if (b) vec_in(c, c->b_orig, b, true, mem);
+    if (cv) vec_in(c, c->c_orig, cv, false, mem);
     apply_rhs_scaling(c);
     sync(c);
     return PDHG_OK;
@@ -1071,13 +1115,13 @@ int pdhg_set_iterate(pdhg_ctx *c, const double *x, const double *y, int mem) {
     if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
     // scaled start in FP64 scratch: x~ = x / D_c, y~ = y / D_r
     if (x) {
-        copy_in(c, c->xo, x, c->n, mem);
+        vec_in(c, c->xo, x, false, mem);
         launch_ew(c->xo, c->xo, c->dc, c->n, 1, c->stream);
     } else {
         launch_fill(c->xo, 0.0, c->n, c->stream);
     }
     if (y) {
-        copy_in(c, c->yo, y, c->m, mem);
+        vec_in(c, c->yo, y, true, mem);
         launch_ew(c->yo, c->yo, c->dr, c->m, 1, c->stream);
     } else {
         launch_fill(c->yo, 0.0, c->m, c->stream);
@@ -1162,10 +1206,12 @@ int pdhg_get_iterate(pdhg_ctx *c, double *x, double *y, double *z, int mem) {
     double *dx = c->xo, *dy = c->yo, *dz = c->aty_avg;
     if (f32(c))
         launch_unscale_xyz32(c->v32.x, c->v32.y, c->aty_cur, c->act_cs, c->dr,
-                             c->dc, dx, dy, dz, c->m, c->n, c->stream);
+                             c->dc, c->pr, c->pc, dx, dy, dz, c->m, c->n,
+                             c->stream);
     else
         launch_unscale_xyz(c->v64.x, c->v64.y, c->aty_cur, c->act_cs, c->dr,
-                           c->dc, dx, dy, dz, c->m, c->n, c->stream);
+                           c->dc, c->pr, c->pc, dx, dy, dz, c->m, c->n,
+                           c->stream);
     copy_out(c, x, dx, c->n, mem);
     copy_out(c, y, dy, c->m, mem);
     copy_out(c, z, dz, c->n, mem);
@@ -1177,8 +1223,9 @@ int pdhg_get_iterate(pdhg_ctx *c, double *x, double *y, double *z, int mem) {
 int pdhg_get_scaling(pdhg_ctx *c, double *dr, double *dc, int mem) {
     API_BEGIN(c)
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
-    copy_out(c, dr, c->dr, c->m, mem);
-    copy_out(c, dc, c->dc, c->n, mem);
+    vec_out(c, dr, c->dr, true, mem);
+    sync(c);
+    vec_out(c, dc, c->dc, false, mem);
     sync(c);
     return PDHG_OK;
     API_END(c)
@@ -1243,7 +1290,8 @@ int pdhg_spmv(pdhg_ctx *c, int which, int scaled, int precision,
     const DevCsr &M = which ? c->At : c->A;
     const int64_t nin = M.cols, nout = M.rows;
     double *din = dmalloc<double>(nin), *dout = dmalloc<double>(nout);
-    copy_in(c, din, in, nin, mem);
+    // input in original order -> internal order
+    vec_in(c, din, in, which == 1, mem);
     if (precision == PDHG_FP32) {
         float *i32 = dmalloc<float>(nin), *o32 = dmalloc<float>(nout);
         launch_to_f32(i32, din, nin, c->stream);
@@ -1260,7 +1308,7 @@ int pdhg_spmv(pdhg_ctx *c, int which, int scaled, int precision,
     } else {
         spmv_f64(M, scaled ? M.v64 : M.v_orig, din, dout, c->stream);
     }
-    copy_out(c, out, dout, nout, mem);
+    vec_out(c, out, dout, which == 0, mem);
     sync(c);
     dfree(din);
     dfree(dout);
@@ -1337,6 +1385,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     int64_t inner_total = 0;
     pdhg_kkt K;
     std::memset(&K, 0, sizeof K);
+    c->refine_log.clear();
     try {
         c->levels.clear();
         c->n_slots = 0;
@@ -1345,6 +1394,10 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
         for (r = 0;; ++r) {
             // outer FP64 KKT of (xo, yo) on the original problem
             kkt_pair64(c, xo, yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);
+            if (r > 0 && !c->refine_log.empty()) {
+                // close the previous round's record with the resulting KKT
+                c->refine_log[c->refine_log.size() - 8 + 7] = now_s() - t0;
+            }
             if (K.maxresid <= R.outer_eps) {
                 status = PDHG_CONVERGED;
                 break;
@@ -1403,6 +1456,12 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             reset_solve(c);
             run_iterations(c, R.max_inner_iters, R.max_inner_iters);
             inner_total += c->k_host;
+            pdhg_kkt ik;
+            kkt_of(c, 0, &ik);
+            const double rec[8] = {(double)r, K.maxresid, DP, DD,
+                                   (double)c->k_host, (double)c->status,
+                                   ik.maxresid, now_s() - t0};
+            c->refine_log.insert(c->refine_log.end(), rec, rec + 8);
             launch_refine_update(xo, yo, c->v32.x, c->v32.y, DP, DD, c->m, c->n, c->stream);
         }
     } catch (...) {
@@ -1451,6 +1510,16 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     API_END(c)
 }
 
+int pdhg_refine_log(pdhg_ctx *c, double *out, int cap, int *count) {
+    if (!c) return PDHG_E_ARG;
+    const int k = (int)(c->refine_log.size() / 8);
+    if (count) *count = k;
+    if (out)
+        for (int i = 0; i < k && i < cap; ++i)
+            std::memcpy(out + 8 * i, c->refine_log.data() + 8 * i, 8 * sizeof(double));
+    return PDHG_OK;
+}
+
 // ------------------------------------------------------------ adjoint
 
 }  // extern "C"
@@ -1476,13 +1545,13 @@ void unrolled_forward_T(pdhg_ctx *c, pdhg_tape *tp, const double *x0,
     }
     // scaled start
     if (x0) {
-        copy_in(c, c->xo, x0, n, mem);
+        vec_in(c, c->xo, x0, false, mem);
         launch_ew(c->xo, c->xo, c->dc, n, 1, c->stream);
     } else {
         launch_fill(c->xo, 0.0, n, c->stream);
     }
     if (y0) {
-        copy_in(c, c->yo, y0, m, mem);
+        vec_in(c, c->yo, y0, true, mem);
         launch_ew(c->yo, c->yo, c->dr, m, 1, c->stream);
     } else {
         launch_fill(c->yo, 0.0, m, c->stream);
@@ -1513,7 +1582,7 @@ void unrolled_forward_T(pdhg_ctx *c, pdhg_tape *tp, const double *x0,
     else
         launch_to_f64(xd, w.x, n, c->stream);
     launch_ew(xd, xd, c->dc, n, 0, c->stream);
-    copy_out(c, xK, xd, n, mem);
+    vec_out(c, xK, xd, false, mem);
     sync(c);
     dfree(w.x);
     dfree(w.y);
@@ -1537,7 +1606,7 @@ void unrolled_backward_T(pdhg_tape *tp, const double *gxK, double *gc,
     HIPC(hipMemsetAsync(gbs, 0, m * sizeof(T), c->stream));
     HIPC(hipMemsetAsync(gAs, 0, nnz * sizeof(T), c->stream));
     // dL/dx~_K = D_c dL/dx_K
-    copy_in(c, c->xo, gxK, n, mem);
+    vec_in(c, c->xo, gxK, false, mem);
     launch_ew(c->xo, c->xo, c->dc, n, 0, c->stream);
     if constexpr (sizeof(T) == 8)
         HIPC(hipMemcpyAsync(gx, c->xo, n * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1594,15 +1663,16 @@ void unrolled_backward_T(pdhg_tape *tp, const double *gxK, double *gc,
     };
     widen(gcs, n);
     launch_ew(out, g64, c->dc, n, 0, c->stream);
-    copy_out(c, gc, out, n, mem);
+    vec_out(c, gc, out, false, mem);
     sync(c);
     widen(gbs, m);
     launch_ew(out, g64, c->dr, m, 0, c->stream);
-    copy_out(c, gb, out, m, mem);
+    vec_out(c, gb, out, true, mem);
     sync(c);
     widen(gAs, nnz);
     launch_scale_values(c->A, g64, c->dr, c->dc, out, nullptr, c->stream);
-    copy_out(c, gA, out, nnz, mem);
+    launch_permute(g64, out, c->apos, nnz, c->stream);   // A's original order
+    copy_out(c, gA, g64, nnz, mem);
     sync(c);
     dfree(g64);
     dfree(out);

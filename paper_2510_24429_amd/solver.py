@@ -228,6 +228,15 @@ class Solver:
                 self.ctx)
         return info.asdict()
 
+    def refine_log(self, cap: int = 64) -> np.ndarray:
+        """Rows: round, outer maxresid before it, Delta_P, Delta_D, inner
+        iterations, inner status, inner maxresid, seconds since start."""
+        buf = np.zeros((cap, 8))
+        cnt = C.c_int(0)
+        L.check(self.lib.pdhg_refine_log(self.ctx, buf.ctypes.data_as(C.c_void_p),
+                                         cap, C.byref(cnt)), self.ctx)
+        return buf[:min(cnt.value, cap)]
+
     # ------------------------------------------------------------- kernels
     def spmv(self, which: int, vec, scaled: bool = False, precision: int = L.FP64):
         nin = self.n if which == 0 else self.m

@@ -1,0 +1,175 @@
+"""GPU checks of the FP32 bulk + FP64 refinement path and of the unrolled
+adjoint, against the FP64 CPU oracle and central finite differences."""
+import numpy as np
+import pytest
+
+from paper_2510_24429_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2510_24429_amd.solver import Solver as S
+    return S
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# ------------------------------------------------------------ refinement
+
+@pytest.mark.parametrize("name", ["uniform", "mcf"])
+def test_fp32_refinement_reaches_1e8(Solver, oracle, name):
+    if name == "uniform":
+        lp = lpgen.make("uniform_m500_n1k")
+    else:
+        lp = lpgen.multicommodity(nodes=1500, arcs=6000, commodities=4, seed=2)
+    ref = oracle.solve(lp, eps_rel=1e-9)
+    assert ref.info["status"] == 1
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-8)
+        r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
+                            max_inner_iters=50000)
+        for row in s.refine_log():
+            print("refine round %d outer %.3e DP %.3g DD %.3g inner iters %d "
+                  "status %d inner %.3e t %.2fs" % tuple(row), flush=True)
+        assert r["status"] == 1, r
+        assert r["rounds"] >= 1
+        x, y, z = s.get_iterate()
+        inf = s.info()
+    # the refined point satisfies the tolerance on the original data,
+    # recomputed by the oracle on the CPU
+    kk = oracle.kkt(lp, x, y)
+    assert kk["maxresid"] <= 1e-8, kk
+    assert abs(kk["maxresid"] - r["kkt"]["maxresid"]) <= 1e-12
+    assert np.all(x >= 0)
+    # error against the FP64 oracle's optimum (objective is unique)
+    perr = abs(kk["pobj"] - ref.kkt["pobj"]) / (1 + abs(ref.kkt["pobj"]))
+    assert perr <= 3e-8, perr
+
+
+def test_fp32_bulk_solve_reaches_fp32_accuracy(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-5, precision=1)
+        st = s.solve(200000)
+        assert st == 1
+        x, y, _ = s.get_iterate()
+    assert oracle.kkt(lp, x, y)["maxresid"] <= 1e-5
+
+
+# ------------------------------------------------------------ adjoint
+
+def _adjoint_setup(oracle, lp, ruiz=10):
+    dr, dc, vs = oracle.ruiz(lp, ruiz)
+    eta = 0.9 / oracle.power(lp, vs)
+    return dr, dc, eta
+
+
+def test_unrolled_matches_oracle_reverse_pass(Solver, oracle):
+    lp = lpgen.planted_uniform(m=300, n=700, k=5, seed=41)
+    dr, dc, eta = _adjoint_setup(oracle, lp)
+    K = 60
+    xt = lpgen.target_vector(lp.n, 41)
+    xK_or, L_or, gc_or, gb_or, gA_or = oracle.unrolled(lp, dr, dc, eta, eta, K, xt)
+    with Solver.from_lp(lp) as s:
+        s.configure(ruiz_passes=10, power_iters=5)
+        grads = {}
+        for ck in (1, 7, K):
+            xK, tape = s.unrolled_forward(K, ck, eta, eta)
+            assert rel(xK, xK_or) <= 1e-12
+            gxK = 2 * (xK - xt)
+            grads[ck] = tape.backward(gxK)
+            tape.free()
+    for ck in (1, 7):                    # checkpointing is bitwise invisible
+        for a, b in zip(grads[ck], grads[K]):
+            assert np.array_equal(a, b)
+    gc, gb, gA = grads[K]
+    assert rel(gc, gc_or) <= 1e-9 and rel(gb, gb_or) <= 1e-9 and rel(gA, gA_or) <= 1e-9
+
+
+def test_unrolled_fp32_within_gate(Solver, oracle):
+    lp = lpgen.planted_uniform(m=300, n=700, k=5, seed=42)
+    dr, dc, eta = _adjoint_setup(oracle, lp)
+    K = 60
+    xt = lpgen.target_vector(lp.n, 42)
+    _, _, gc_or, gb_or, gA_or = oracle.unrolled(lp, dr, dc, eta, eta, K, xt)
+    with Solver.from_lp(lp) as s:
+        s.configure(ruiz_passes=10, power_iters=5)
+        xK, tape = s.unrolled_forward(K, 20, eta, eta, precision=1)
+        gc, gb, gA = tape.backward(2 * (xK - xt))
+    assert rel(gc, gc_or) <= 1e-3 and rel(gb, gb_or) <= 1e-3 and rel(gA, gA_or) <= 1e-3
+
+
+def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
+    """The adjoint workload at full size: m=50k, n=100k, 8 nonzeros per
+    column, K=200 steps, checkpoint every 20, loss ||x_K - x_t||^2."""
+    import torch
+    from paper_2510_24429_amd.autograd import PDHGUnroll
+    lp = lpgen.make("uniform_m50k_n100k_k8")
+    dr, dc, eta = _adjoint_setup(oracle, lp)
+    K, ck, h = 200, 20, 1e-6
+    xt = lpgen.target_vector(lp.n, 3)
+    xK_or, L_or, gc_or, gb_or, gA_or = oracle.unrolled(lp, dr, dc, eta, eta, K, xt)
+    s = Solver.from_lp(lp)
+    s.configure(ruiz_passes=10, power_iters=5)
+    dev = torch.device("cuda:0")
+    c = torch.tensor(lp.c, device=dev, requires_grad=True)
+    b = torch.tensor(lp.b, device=dev, requires_grad=True)
+    av = torch.tensor(lp.a_v, device=dev, requires_grad=True)
+    xK = PDHGUnroll.apply(c, b, av, s, K, ck, eta, eta)
+    loss = ((xK - torch.tensor(xt, device=dev)) ** 2).sum()
+    loss.backward()
+    gc, gb, gA = (t.grad.cpu().numpy() for t in (c, b, av))
+    assert rel(xK.detach().cpu().numpy(), xK_or) <= 1e-12
+    assert abs(loss.item() - L_or) <= 1e-10 * L_or
+    assert rel(gc, gc_or) <= 1e-9 and rel(gb, gb_or) <= 1e-9 and rel(gA, gA_or) <= 1e-9
+
+    # central differences on 64 random coordinates per group; the loss
+    # difference is formed elementwise (sum (x+ - x-)(x+ + x- - 2 t) / 2h).
+    # A coordinate whose +-h runs flip a projection mask sits at a kink of
+    # the piecewise-linear map: it is skipped (and redrawn) when the oracle's
+    # forward pass confirms the flip
+    _, h0 = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K)
+    rng = np.random.default_rng(7)
+
+    def fwd_gpu(cv, bv, vv):
+        s.set_values(vv)
+        s.set_rhs_obj(bv, cv)
+        x, tape = s.unrolled_forward(K, K, eta, eta)
+        tape.free()
+        return x
+
+    vals = {"c": lp.c, "b": lp.b, "A": lp.a_v}
+    for group, g, size in (("c", gc, lp.n), ("b", gb, lp.m), ("A", gA, lp.nnz)):
+        done, errs, tries, kinks = 0, [], 0, 0
+        while done < 64 and tries < 200:
+            tries += 1
+            t = int(rng.integers(size))
+            p = {k: v.copy() for k, v in vals.items()}
+            q = {k: v.copy() for k, v in vals.items()}
+            p[group][t] += h
+            q[group][t] -= h
+            xp = fwd_gpu(p["c"], p["b"], p["A"])
+            xm = fwd_gpu(q["c"], q["b"], q["A"])
+            fd = np.sum((xp - xm) * (xp + xm - 2 * xt)) / (2 * h)
+            scale = max(abs(g[t]), 1e-3 * np.max(np.abs(g)))
+            err = abs(fd - g[t]) / scale
+            if err > 1e-6:
+                kw = {"c": "c", "b": "b", "A": "vals"}[group]
+                _, hp = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K, **{kw: p[group]})
+                _, hm = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K, **{kw: q[group]})
+                if hp != h0 or hm != h0:
+                    kinks += 1
+                    continue
+            errs.append(err)
+            done += 1
+        assert done == 64, (group, done, kinks)
+        assert max(errs) <= 1e-6, (group, max(errs))
+    fwd_gpu(lp.c, lp.b, lp.a_v)
+    s.close()
