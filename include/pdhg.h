@@ -136,6 +136,9 @@ typedef struct {
     int32_t max_rounds;         /* refinement rounds after round 0 (8) */
     int32_t cap_log2;           /* scale growth cap per round, 2^cap (10) */
     int64_t max_inner_iters;    /* per inner solve (200000) */
+    double progress;            /* an inner solve also stops once the refined
+                                   point's FP64 maxresid <= max(outer_eps,
+                                   progress * maxresid before the round) (1e-3) */
 } pdhg_refine_params;
 
 typedef struct {
@@ -283,7 +286,10 @@ int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
  * LP  min (Delta_D d)^T xh  s.t.  A xh = Delta_P r_P,  xh >= -Delta_P x
  * with FP32 bulk iterations and FP64 evaluations, and updates in FP64
  * x <- max(0, x + xh / Delta_P), y <- y + yh / Delta_D, until the FP64
- * maxresid <= outer_eps.  Uses the parameters of the last configure (its
+ * maxresid <= outer_eps.  An inner solve stops at inner_eps or when the
+ * refined point has gained the factor `progress`; a round after the first
+ * starts from the previous round's final primal weight rescaled by the change
+ * of Delta_D / Delta_P.  Uses the parameters of the last configure (its
  * precision field is ignored).  The refined iterate becomes the context's
  * current iterate. */
 int pdhg_solve_refined(pdhg_ctx *ctx, const pdhg_refine_params *rp,

@@ -218,7 +218,7 @@ def solve(lp, levels: Sequence[float] = (), l=None, x0=None, y0=None,
 
 
 def refine(lp, outer_eps: float = 1e-8, max_rounds: int = 8,
-           cap_log2: int = 10, **inner_kw):
+           cap_log2: int = 10, progress: float = 1e-3, **inner_kw):
     """FP64 iterative refinement with FP64 inner solves (logic check)."""
     rp, ci, v = _csr(lp)
     kw = dict(eps_rel=1e-4)
@@ -233,7 +233,8 @@ def refine(lp, outer_eps: float = 1e-8, max_rounds: int = 8,
                          _p(ci, np.int32), _p(v),
                          _p(np.ascontiguousarray(lp.b)),
                          _p(np.ascontiguousarray(lp.c)), C.byref(prm),
-                         C.c_double(outer_eps), C.c_int32(max_rounds),
+                         C.c_double(outer_eps), C.c_double(progress),
+                         C.c_int32(max_rounds),
                          C.c_int32(cap_log2), _p(x), _p(y), C.byref(K),
                          C.byref(rounds), C.byref(inner), _p(rlog))
     return dict(status=st, x=x, y=y, kkt=K.asdict(), rounds=rounds.value,

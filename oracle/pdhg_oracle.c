@@ -378,14 +378,40 @@ static void write_unscaled(prob_t *P, const double *xs, const double *ys,
  * the candidate with the smaller maxresid; then the adaptive restart rule runs
  * on KKT_omega.  Inputs x0/y0 and outputs are unscaled.
  */
-int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
-             const double *v, const double *b, const double *c,
-             const double *l, const double *x0, const double *y0,
-             const or_params *prm, or_info *info, double *x_out,
-             double *y_out, double *z_out, or_snap *snaps, double *snap_x,
-             double *snap_y, double *snap_z, int32_t trace_k,
+/* Outer-progress test used by refinement: the inner iterate (xs, ys) of a
+ * correction LP maps to the refined point x = max(0, xo + D_c xs / DP),
+ * y = yo + D_r ys / DD, whose KKT on the original data (A, bo, co) is
+ * compared with `target`. */
+typedef struct {
+    const double *xo, *yo, *bo, *co;
+    double DP, DD, nbo, nco, target;
+} outer_t;
+
+static int outer_reached(const or_pattern *A, const double *v,
+                         const double *dr, const double *dc,
+                         const double *xs, const double *ys,
+                         const outer_t *o) {
+    int64_t m = A->m, n = A->n;
+    double *x = dalloc(n), *y = dalloc(m), *wm = dalloc(m), *wn = dalloc(n);
+    for (int64_t j = 0; j < n; ++j) {
+        double t = o->xo[j] + (dc[j] * xs[j]) / o->DP;
+        x[j] = t < 0.0 ? 0.0 : t;
+    }
+    for (int64_t i = 0; i < m; ++i) y[i] = o->yo[i] + (dr[i] * ys[i]) / o->DD;
+    or_kkt_t K;
+    kkt_unscaled(A, v, o->bo, o->co, NULL, o->nbo, o->nco, x, y, wm, wn, &K);
+    free(x); free(y); free(wm); free(wn);
+    return K.maxresid <= o->target;
+}
+
+static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
+             const int32_t *ci, const double *v, const double *b,
+             const double *c, const double *l, const double *x0,
+             const double *y0, const or_params *prm, or_info *info,
+             double *x_out, double *y_out, double *z_out, or_snap *snaps,
+             double *snap_x, double *snap_y, double *snap_z, int32_t trace_k,
              double *trace_x, double *trace_y, int32_t log_cap,
-             double *eval_log) {
+             double *eval_log, const outer_t *outer) {
     double t0 = now_s();
     or_pattern A = {m, n, rp, ci};
     int64_t nnz = rp[m];
@@ -556,6 +582,13 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
                 e[3] = Kc_cur; e[4] = Kc_avg; e[5] = (double)restarted;
                 e[6] = (double)cand; e[7] = omega;
             }
+            /* refinement: stop as soon as the refined point has made the
+               required progress on the original problem */
+            if (status == OR_RUNNING && outer &&
+                outer_reached(&A, v, dr, dc, xs, ys, outer)) {
+                status = OR_CONVERGED;
+                returned = 0;
+            }
             if (status == OR_RUNNING && prm->time_limit_s > 0.0 &&
                 now_s() - t0 > prm->time_limit_s)
                 status = OR_TIME_LIMIT;
@@ -567,7 +600,7 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
     }
     double t2 = now_s();
 
-    if (status != OR_CONVERGED) {
+    if (status != OR_CONVERGED || (outer && returned == 0)) {
         cand_t S;
         eval_cand(&P, xs, ys, xl, yl, &S);
         final_kkt = S.kkt;
@@ -599,6 +632,19 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
     return 0;
 }
 
+int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
+             const double *v, const double *b, const double *c,
+             const double *l, const double *x0, const double *y0,
+             const or_params *prm, or_info *info, double *x_out,
+             double *y_out, double *z_out, or_snap *snaps, double *snap_x,
+             double *snap_y, double *snap_z, int32_t trace_k,
+             double *trace_x, double *trace_y, int32_t log_cap,
+             double *eval_log) {
+    return solve_impl(m, n, rp, ci, v, b, c, l, x0, y0, prm, info, x_out,
+                      y_out, z_out, snaps, snap_x, snap_y, snap_z, trace_k,
+                      trace_x, trace_y, log_cap, eval_log, NULL);
+}
+
 /* ------------------------------------------------------ refinement ----- */
 
 /*
@@ -610,19 +656,30 @@ int or_solve(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
  * (the capped value when delta = 0), solves the correction LP
  *   min (Delta_D d)^T xh  s.t.  A xh = Delta_P r_P,  xh >= -Delta_P x
  * and updates x <- max(0, x + xh / Delta_P), y <- y + yh / Delta_D.
- * The inner solver is or_solve (FP64 here) with the inner parameters.
+ * The inner solver is the PDHG above (FP64 here) with the inner parameters,
+ * and two choices made for PDHG inner solves:
+ *  - the inner solve also stops once the refined point reaches
+ *    max(outer_eps, progress * maxresid before the round) on the original
+ *    LP (checked at every inner evaluation), since the correction LP's own
+ *    relative criteria are diluted by the large scaled reduced costs of
+ *    nonbasic columns;
+ *  - a round r >= 1 starts from the previous inner solve's final primal
+ *    weight times (Delta_D / Delta_D,prev) / (Delta_P / Delta_P,prev): the
+ *    correction's dual and primal solutions scale by Delta_D and Delta_P,
+ *    while ||c^|| / ||b^|| is dominated by those reduced costs.
  */
 int or_refine(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
               const double *v, const double *b, const double *c,
-              const or_params *inner, double outer_eps, int32_t max_rounds,
-              int32_t cap_log2, double *x, double *y, or_kkt_t *final_kkt,
-              int32_t *rounds_done, int64_t *inner_iters, double *round_log) {
+              const or_params *inner, double outer_eps, double progress,
+              int32_t max_rounds, int32_t cap_log2, double *x, double *y,
+              or_kkt_t *final_kkt, int32_t *rounds_done, int64_t *inner_iters,
+              double *round_log) {
     or_pattern A = {m, n, rp, ci};
     double *rpv = dalloc(m), *d = dalloc(n), *bh = dalloc(m), *ch = dalloc(n),
            *lh = dalloc(n), *xh = dalloc(n), *yh = dalloc(m), *zh = dalloc(n),
            *wm = dalloc(m), *wn = dalloc(n);
     double nb = nrm2(b, m), nc = nrm2(c, n);
-    double DP = 1.0, DD = 1.0;
+    double DP = 1.0, DD = 1.0, DPprev = 1.0, DDprev = 1.0, omega_end = 0.0;
     int64_t total = 0;
     int r = 0, status = OR_ITER_LIMIT;
     for (int64_t j = 0; j < n; ++j) x[j] = 0.0;
@@ -648,6 +705,8 @@ int or_refine(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
             for (int64_t i = 0; i < m; ++i) if (fabs(rpv[i]) > dP) dP = fabs(rpv[i]);
             for (int64_t j = 0; j < n; ++j) if (-x[j] > dP) dP = -x[j];
             for (int64_t j = 0; j < n; ++j) if (-d[j] > dD) dD = -d[j];
+            DPprev = DP;
+            DDprev = DD;
             double capP = ldexp(DP, cap_log2), capD = ldexp(DD, cap_log2);
             double sP = dP > 0.0 ? ldexp(1.0, (int)floor(log2(1.0 / dP))) : capP;
             double sD = dD > 0.0 ? ldexp(1.0, (int)floor(log2(1.0 / dD))) : capD;
@@ -661,9 +720,14 @@ int or_refine(int64_t m, int64_t n, const int64_t *rp, const int32_t *ci,
         or_snap dummy;
         or_params ip = *inner;
         ip.n_levels = 0;
-        int rc = or_solve(m, n, rp, ci, v, bh, ch, lh, NULL, NULL, &ip, &info,
-                          xh, yh, zh, &dummy, NULL, NULL, NULL, 0, NULL, NULL,
-                          0, NULL);
+        if (r >= 1 && omega_end > 0.0)
+            ip.omega0 = omega_end * (DD / DDprev) / (DP / DPprev);
+        outer_t oc = {x, y, b, c, DP, DD, nb, nc,
+                      fmax(outer_eps, progress * K.maxresid)};
+        int rc = solve_impl(m, n, rp, ci, v, bh, ch, lh, NULL, NULL, &ip,
+                            &info, xh, yh, zh, &dummy, NULL, NULL, NULL, 0,
+                            NULL, NULL, 0, NULL, &oc);
+        omega_end = info.omega;
         if (rc != 0) { status = rc; break; }
         total += info.iters;
         for (int64_t j = 0; j < n; ++j) {

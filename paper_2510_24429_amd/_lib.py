@@ -80,7 +80,7 @@ class SnapInfo(C.Structure):
 class RefineParams(C.Structure):
     _fields_ = [("outer_eps", C.c_double), ("inner_eps", C.c_double),
                 ("max_rounds", C.c_int32), ("cap_log2", C.c_int32),
-                ("max_inner_iters", C.c_int64)]
+                ("max_inner_iters", C.c_int64), ("progress", C.c_double)]
 
 
 class RefineInfo(C.Structure):

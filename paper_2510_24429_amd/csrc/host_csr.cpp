@@ -52,6 +52,7 @@ extern "C" int pdhg_refine_params_default(pdhg_refine_params *p) {
     p->max_rounds = 8;
     p->cap_log2 = 10;
     p->max_inner_iters = 200000;
+    p->progress = 1e-3;
     return PDHG_OK;
 }
 

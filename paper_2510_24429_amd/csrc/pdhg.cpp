@@ -141,6 +141,9 @@ struct pdhg_ctx {
     std::atomic<int> cancel_flag{0};
     std::vector<SnapMeta> snaps;
     std::vector<double> refine_log;   // 8 doubles per refinement round
+    // outer-progress test of a refinement inner solve (active when set)
+    const double *ref_xo = nullptr, *ref_yo = nullptr;
+    double ref_DP = 1.0, ref_DD = 1.0, ref_target = -1.0;
 
     // callback thread
     void (*cb)(void *, int, const pdhg_snapshot_info *) = nullptr;
@@ -707,6 +710,21 @@ void collect_snapshots(pdhg_ctx *c) {
     c->cb_cv.notify_one();
 }
 
+void kkt_pair64(pdhg_ctx *c, const double *xs, const double *ys,
+                const double *bs, const double *cs, const double *ls,
+                double nb, double nc, pdhg_kkt *out);
+
+// Refinement: has the refined point max(0, xo + x^/DP), yo + y^/DD of the
+// current inner iterate reached the round's target on the original LP?
+bool refine_outer_reached(pdhg_ctx *c) {
+    HIPC(hipMemcpyAsync(c->xo, c->ref_xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPC(hipMemcpyAsync(c->yo, c->ref_yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    launch_refine_update(c->xo, c->yo, c->v32.x, c->v32.y, c->ref_DP, c->ref_DD, c->m, c->n, c->stream);
+    pdhg_kkt K;
+    kkt_pair64(c, c->xo, c->yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);
+    return K.maxresid <= c->ref_target;
+}
+
 // The iteration loop shared by pdhg_iterate and the refinement's inner
 // solves.  Runs until the status leaves RUNNING or `max_more` iterations.
 int run_iterations(pdhg_ctx *c, int64_t max_more, int64_t limit_total) {
@@ -748,6 +766,12 @@ int run_iterations(pdhg_ctx *c, int64_t max_more, int64_t limit_total) {
             c->status = c->st_host->status;
             c->k_host = c->st_host->k;
             collect_snapshots(c);
+            if (c->status == PDHG_RUNNING && c->ref_target >= 0.0 &&
+                refine_outer_reached(c)) {
+                launch_set_status(c->st, PDHG_CONVERGED, c->stream);
+                read_state(c);
+                c->status = c->st_host->status;
+            }
             if (c->status == PDHG_RUNNING) {
                 int stop = 0;
                 if (c->cancel_flag.load()) stop = PDHG_CANCELLED;
@@ -1380,7 +1404,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     const pdhg_params saved = c->params;
     const std::vector<double> saved_levels = c->levels;
     const int saved_slots = c->n_slots;
-    double DP = 1.0, DD = 1.0;
+    double DP = 1.0, DD = 1.0, DPprev = 1.0, DDprev = 1.0, omega_end = 0.0;
     int status = PDHG_ITER_LIMIT, r = 0;
     int64_t inner_total = 0;
     pdhg_kkt K;
@@ -1419,6 +1443,8 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
                 double d2[2];
                 HIPC(hipMemcpyAsync(d2, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
                 sync(c);
+                DPprev = DP;
+                DDprev = DD;
                 const double capP = std::ldexp(DP, R.cap_log2), capD = std::ldexp(DD, R.cap_log2);
                 auto pow2floor_inv = [](double d) {
                     int e = 0;
@@ -1440,7 +1466,8 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             launch_norm_unscaled(c->ch, c->dc, c->n, c->partial, c->scal, c->stream);
             const double nch = std::sqrt(read_scalar(c, c->scal));
             const double nbs = dev_norm(c, c->bh, c->m), ncs = dev_norm(c, c->ch, c->n);
-            const double om = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
+            double om = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
+            if (r >= 1 && omega_end > 0.0) om = omega_end * (DD / DDprev) / (DP / DPprev);
             // inner solve of the correction LP with FP32 bulk iterations
             c->prec = PDHG_FP32;
             c->act_bs = c->bh;
@@ -1454,7 +1481,14 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             State s = fresh_state(c, om, nbh, nch);
             write_state(c, s);
             reset_solve(c);
+            c->ref_xo = xo;
+            c->ref_yo = yo;
+            c->ref_DP = DP;
+            c->ref_DD = DD;
+            c->ref_target = std::max(R.outer_eps, R.progress * K.maxresid);
             run_iterations(c, R.max_inner_iters, R.max_inner_iters);
+            c->ref_target = -1.0;
+            omega_end = c->st_host->omega;
             inner_total += c->k_host;
             pdhg_kkt ik;
             kkt_of(c, 0, &ik);
@@ -1465,6 +1499,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             launch_refine_update(xo, yo, c->v32.x, c->v32.y, DP, DD, c->m, c->n, c->stream);
         }
     } catch (...) {
+        c->ref_target = -1.0;
         c->params = saved;
         c->levels = saved_levels;
         c->n_slots = saved_slots;
