@@ -52,7 +52,7 @@ def main():
     ap.add_argument("--workload", default="powerlaw_m200k_n1m")
     ap.add_argument("--no-ttk", action="store_true", help="skip time-to-KKT runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle")
-    ap.add_argument("--ttk-cap", type=float, default=90.0,
+    ap.add_argument("--ttk-cap", type=float, default=60.0,
                     help="seconds allowed per time-to-KKT run")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
@@ -209,7 +209,8 @@ def time_to_kkt(Solver, lp, cap):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.configure(eps_rel=1e-8, time_limit_s=cap)
-        r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8)
+        r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
+                            max_inner_iters=5_000_000)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         res["fp32_refine"] = {"seconds": round(t, 3), "status": r["status"],

@@ -290,7 +290,8 @@ int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
  * refined point has gained the factor `progress`; a round after the first
  * starts from the previous round's final primal weight rescaled by the change
  * of Delta_D / Delta_P.  Uses the parameters of the last configure (its
- * precision field is ignored).  The refined iterate becomes the context's
+ * precision field is ignored; its time_limit_s bounds the whole
+ * refinement).  The refined iterate becomes the context's
  * current iterate. */
 int pdhg_solve_refined(pdhg_ctx *ctx, const pdhg_refine_params *rp,
                        pdhg_refine_info *info);

@@ -24,6 +24,26 @@ __device__ __forceinline__ T ntload(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Four consecutive streamed entries starting at a multiple of 4, as 16-byte
+// loads (index arrays and value arrays are padded to a multiple of 4).
+__device__ __forceinline__ void ld4(const int32_t *p, int (&o)[4]) {
+    const v4i v = __builtin_nontemporal_load((const v4i *)p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double (&o)[4]) {
+    const v2d a = __builtin_nontemporal_load((const v2d *)p);
+    const v2d b = __builtin_nontemporal_load((const v2d *)(p + 2));
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void ld4(const float *p, float (&o)[4]) {
+    const v4f v = __builtin_nontemporal_load((const v4f *)p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -72,6 +92,12 @@ struct SpmvElem {
     __device__ __forceinline__ void fetch(int p, int &j, MT &a) const {
         j = ntload(ci + p);
         a = ntload(v + p);
+    }
+    // entries base..base+3 (base a multiple of 4)
+    __device__ __forceinline__ void fetch4(int base, int (&j)[4],
+                                           MT (&a)[4]) const {
+        ld4(ci + base, j);
+        ld4(v + base, a);
     }
     __device__ __forceinline__ Acc apply(int j, MT a) const {
         return (Acc)a * (Acc)x[j];
@@ -199,34 +225,44 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
     const RowBlock b = blks[blockIdx.x];
     const int tid = threadIdx.x;
     if (b.r1 - b.r0 == 1) {
-        // one row: the workgroup strides it, four loads in flight per lane
+        // one row: the workgroup strides it in aligned groups of four
+        // nonzeros per lane (16-byte index and value loads), two groups in
+        // flight; entries outside [p0, p1) are masked and never gathered
         int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
         if (b.nparts > 1) {
             const int chunk = (p1 - p0 + b.nparts - 1) / b.nparts;
             p0 = p0 + b.part * chunk;
             p1 = min(p1, p0 + chunk);
         }
-        Acc s0 = (Acc)0, s1 = (Acc)0, s2 = (Acc)0, s3 = (Acc)0;
-        int p = p0 + tid;
-        for (; p + 3 * kWG < p1; p += 4 * kWG) {
-            int j0, j1, j2, j3;
-            MT a0, a1, a2, a3;
-            elem.fetch(p, j0, a0);
-            elem.fetch(p + kWG, j1, a1);
-            elem.fetch(p + 2 * kWG, j2, a2);
-            elem.fetch(p + 3 * kWG, j3, a3);
-            s0 += elem.apply(j0, a0);
-            s1 += elem.apply(j1, a1);
-            s2 += elem.apply(j2, a2);
-            s3 += elem.apply(j3, a3);
+        Acc s0 = (Acc)0, s1 = (Acc)0;
+        int base = (p0 & ~3) + 4 * tid;
+        for (; base + 4 * kWG < p1; base += 8 * kWG) {
+            int j0[4], j1[4];
+            MT a0[4], a1[4];
+            elem.fetch4(base, j0, a0);
+            elem.fetch4(base + 4 * kWG, j1, a1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = base + u;
+                if (p >= p0) s0 += elem.apply(j0[u], a0[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = base + 4 * kWG + u;
+                if (p < p1) s1 += elem.apply(j1[u], a1[u]);
+            }
         }
-        for (; p < p1; p += kWG) {
-            int j0;
-            MT a0;
-            elem.fetch(p, j0, a0);
-            s0 += elem.apply(j0, a0);
+        if (base < p1) {
+            int j0[4];
+            MT a0[4];
+            elem.fetch4(base, j0, a0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = base + u;
+                if (p >= p0 && p < p1) s0 += elem.apply(j0[u], a0[u]);
+            }
         }
-        Acc s = block_sum((s0 + s1) + (s2 + s3), s_red);
+        Acc s = block_sum(s0 + s1, s_red);
         if (tid == 0) {
             if (b.nparts > 1)
                 part[b.slot * maxparts + b.part] = s;
@@ -235,22 +271,29 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
         }
         return;
     }
-    // several rows: stream their nonzeros (contiguous, <= TILE) into LDS,
-    // all index/value loads first, then all gathers
+    // several rows: stream their nonzeros (contiguous, <= TILE - 3) into LDS
+    // in aligned groups of four per lane (16-byte loads), index and value
+    // loads first, then the gathers
     const int p0 = rp[b.r0];
     const int nz = rp[b.r1] - p0;
     {
-        int jj[U];
-        MT aa[U];
+        const int a0 = p0 & ~3;
+        constexpr int G4 = U / 4;      // groups of four per lane
+        int jj[G4][4];
+        MT aa[G4][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int q = tid + u * kWG;
-            if (q < nz) elem.fetch(p0 + q, jj[u], aa[u]);
+        for (int g = 0; g < G4; ++g) {
+            const int base = a0 + 4 * (tid + g * kWG);
+            if (base < p0 + nz) elem.fetch4(base, jj[g], aa[g]);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int q = tid + u * kWG;
-            if (q < nz) s_prod[q] = elem.apply(jj[u], aa[u]);
+        for (int g = 0; g < G4; ++g) {
+            const int base = a0 + 4 * (tid + g * kWG);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = base + u - p0;
+                if (q >= 0 && q < nz) s_prod[q] = elem.apply(jj[g][u], aa[g][u]);
+            }
         }
     }
     __syncthreads();

@@ -344,18 +344,27 @@ void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
     M.nnz = nnz;
     std::vector<int32_t> rp32((size_t)rows + 1);
     for (int64_t i = 0; i <= rows; ++i) rp32[i] = (int32_t)rp[i];
+    // index and value arrays padded (zeros) to a multiple of 4 plus 4, so the
+    // kernels' aligned 16-byte group loads stay inside the allocation
+    const int64_t pad = ((nnz + 3) & ~(int64_t)3) + 4;
     M.rp = dmalloc<int32_t>(rows + 1);
-    M.ci = dmalloc<int32_t>(nnz);
-    M.v_orig = dmalloc<double>(nnz);
-    M.v64 = dmalloc<double>(nnz);
-    M.v32 = dmalloc<float>(nnz);
+    M.ci = dmalloc<int32_t>(pad);
+    M.v_orig = dmalloc<double>(pad);
+    M.v64 = dmalloc<double>(pad);
+    M.v32 = dmalloc<float>(pad);
+    HIPC(hipMemset(M.ci, 0, pad * sizeof(int32_t)));
+    HIPC(hipMemset(M.v_orig, 0, pad * sizeof(double)));
+    HIPC(hipMemset(M.v64, 0, pad * sizeof(double)));
+    HIPC(hipMemset(M.v32, 0, pad * sizeof(float)));
     HIPC(hipMemcpy(M.rp, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     if (nnz > 0) {
         HIPC(hipMemcpy(M.ci, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPC(hipMemcpy(M.v_orig, v.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
     }
-    HostBins b64 = build_row_blocks(rows, rp.data(), kTile64, c->split_threshold, c->split_chunk);
-    HostBins b32 = build_row_blocks(rows, rp.data(), kTile32, c->split_threshold, c->split_chunk);
+    // multi-row blocks hold at most TILE - 3 nonzeros: an aligned window of
+    // TILE entries then always covers them
+    HostBins b64 = build_row_blocks(rows, rp.data(), kTile64 - 3, c->split_threshold, c->split_chunk);
+    HostBins b32 = build_row_blocks(rows, rp.data(), kTile32 - 3, c->split_threshold, c->split_chunk);
     M.nblk64 = (int)b64.blocks.size();
     M.nblk32 = (int)b32.blocks.size();
     M.blk64 = dmalloc<RowBlock>(M.nblk64);
@@ -1435,6 +1444,13 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
                 status = PDHG_CANCELLED;
                 break;
             }
+            // the configure time limit bounds the whole refinement
+            const double left = saved.time_limit_s - (now_s() - t0);
+            if (saved.time_limit_s > 0.0 && left <= 0.0) {
+                status = PDHG_TIME_LIMIT;
+                break;
+            }
+            c->params.time_limit_s = saved.time_limit_s > 0.0 ? left : 0.0;
             // ax_cur = A~ xo, aty_cur = A~^T yo from kkt_pair64
             if (r >= 1) {
                 launch_refine_delta(c->bs, c->ax_cur, c->cs, c->aty_cur, xo,
