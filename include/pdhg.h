@@ -185,6 +185,16 @@ int pdhg_check_transpose(int64_t m, int64_t n, int64_t nnz,
                          const int32_t *at_ci, const double *at_v,
                          int64_t *perm, char *msg, int msg_len);
 
+/* Row-length bins of one CSR matrix (rows+1 int64 row pointers) for a tile
+ * of `tile` nonzeros: writes up to cap descriptors of 4 int32 each
+ * (first row, end row, part, number of parts) in launch order and returns
+ * the number of descriptors (or a negative error).  Rows longer than
+ * split_threshold are split into parts of split_chunk nonzeros.  Host only;
+ * the library calls the same planner at load time. */
+int pdhg_plan_bins(int64_t rows, const int64_t *rp, int tile,
+                   int64_t split_threshold, int64_t split_chunk,
+                   int32_t *out, int64_t cap);
+
 /* ---- context lifecycle ------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t

@@ -114,6 +114,7 @@ SIGNATURES = {
     "pdhg_validate_csr": (i32, [i64, i64, i64, vp, vp, C.c_char_p, i32]),
     "pdhg_check_transpose": (i32, [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp,
                                    C.c_char_p, i32]),
+    "pdhg_plan_bins": (i32, [i64, vp, i32, i64, i64, vp, i64]),
     "pdhg_create": (i32, [i32, vp, C.POINTER(vp)]),
     "pdhg_destroy": (None, [vp]),
     "pdhg_last_error": (C.c_char_p, [vp]),

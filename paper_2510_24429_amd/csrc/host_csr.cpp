@@ -179,6 +179,24 @@ extern "C" int pdhg_check_transpose(int64_t m, int64_t n, int64_t nnz,
     return PDHG_OK;
 }
 
+extern "C" int pdhg_plan_bins(int64_t rows, const int64_t *rp, int tile,
+                              int64_t split_threshold, int64_t split_chunk,
+                              int32_t *out, int64_t cap) {
+    if (rows < 1 || !rp || tile < 1 || split_chunk < 1 ||
+        split_threshold < tile)
+        return PDHG_E_ARG;
+    pdhg::HostBins hb =
+        pdhg::build_row_blocks(rows, rp, tile, split_threshold, split_chunk);
+    const int64_t k = (int64_t)hb.blocks.size();
+    for (int64_t i = 0; i < k && i < cap && out; ++i) {
+        out[4 * i + 0] = hb.blocks[i].r0;
+        out[4 * i + 1] = hb.blocks[i].r1;
+        out[4 * i + 2] = hb.blocks[i].part;
+        out[4 * i + 3] = hb.blocks[i].nparts;
+    }
+    return (int)k;
+}
+
 namespace pdhg {
 
 // Row-length bins.  Consecutive rows are packed into multi-row blocks of at

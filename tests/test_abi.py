@@ -150,3 +150,47 @@ def test_loading_without_gpu_reports_device_error():
     ctx = C.c_void_p()
     rc = L.lib().pdhg_create(0, None, C.byref(ctx))
     assert rc < 0 and not ctx.value
+
+
+def _plan(rp, tile, thr, chunk):
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    cap = 4 * len(rp) + 1000
+    out = np.zeros(4 * cap, dtype=np.int32)
+    k = L.lib().pdhg_plan_bins(len(rp) - 1, rp.ctypes.data_as(C.c_void_p), tile,
+                               thr, chunk, out.ctypes.data_as(C.c_void_p), cap)
+    assert k > 0
+    return out[:4 * k].reshape(k, 4)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_row_bins_cover_every_row_once(seed):
+    rng = np.random.default_rng(seed)
+    lens = np.concatenate([np.zeros(30, dtype=np.int64), rng.integers(1, 20, 3000),
+                           rng.integers(20, 1100, 300), rng.integers(1100, 9000, 30),
+                           np.array([50_000, 123_457])])
+    rng.shuffle(lens)
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    tile, thr, chunk = 1021, 40_000, 10_000
+    blk = _plan(rp, tile, thr, chunk)
+    covered = np.zeros(len(lens), dtype=np.int64)
+    seen_long = True
+    for r0, r1, part, nparts in blk:
+        assert 0 <= r0 < r1 <= len(lens)
+        if r1 - r0 > 1 or nparts == 1:
+            if part == 0:
+                covered[r0:r1] += 1
+        nz = rp[r1] - rp[r0]
+        if r1 - r0 > 1:
+            seen_long = False
+            assert nz <= tile and r1 - r0 <= tile      # fits the LDS tile
+        else:
+            assert seen_long or lens[r0] <= tile     # long rows come first
+            if nparts > 1:
+                assert lens[r0] > thr and nparts == -(-lens[r0] // chunk)
+                if part == 0:
+                    covered[r0] += 1
+    assert np.all(covered == 1)
+    # split parts of one row are all present, in order
+    for row in np.nonzero(lens > thr)[0]:
+        parts = blk[(blk[:, 0] == row) & (blk[:, 3] > 1)][:, 2]
+        assert list(parts) == list(range(len(parts)))
