@@ -219,6 +219,8 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
     constexpr int U = TILE / kWG;     // nonzeros per thread in a full tile
     using MT = decltype(elem.v[0] + 0);
     __shared__ Acc s_prod[TILE];
+    __shared__ Acc s_sum[kWG];
+    __shared__ int s_rp[TILE + 1];
     __shared__ Acc s_red[4];
     Epi epi = epi_in;
     if (!epi.begin()) return;
@@ -271,11 +273,13 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
         }
         return;
     }
-    // several rows: stream their nonzeros (contiguous, <= TILE - 3) into LDS
-    // in aligned groups of four per lane (16-byte loads), index and value
-    // loads first, then the gathers
+    // several rows: stage their row pointers in LDS, stream their nonzeros
+    // (contiguous, <= TILE - 3) into LDS in aligned groups of four per lane
+    // (16-byte loads), index and value loads first, then the gathers
+    const int R = b.r1 - b.r0;
     const int p0 = rp[b.r0];
     const int nz = rp[b.r1] - p0;
+    for (int r = tid; r <= R; r += kWG) s_rp[r] = rp[b.r0 + r] - p0;
     {
         const int a0 = p0 & ~3;
         constexpr int G4 = U / 4;      // groups of four per lane
@@ -297,23 +301,26 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
         }
     }
     __syncthreads();
-    const int R = b.r1 - b.r0;
     if (R <= kWG) {
+        // a power-of-two group of lanes per row sums it from LDS
         int G = 64;
         while (G * R > kWG) G >>= 1;
         const int r = tid / G, lane = tid & (G - 1);
         Acc s = (Acc)0;
         if (r < R) {
-            const int q0 = rp[b.r0 + r] - p0, q1 = rp[b.r0 + r + 1] - p0;
-            for (int q = q0 + lane; q < q1; q += G) s += s_prod[q];
+            const int q1 = s_rp[r + 1];
+            for (int q = s_rp[r] + lane; q < q1; q += G) s += s_prod[q];
         }
         for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (r < R && lane == 0) epi(b.r0 + r, s);
+        if (r < R && lane == 0) s_sum[r] = s;
+        __syncthreads();
+        // epilogue on consecutive rows by consecutive threads
+        if (tid < R) epi(b.r0 + tid, s_sum[tid]);
     } else {
         for (int r = tid; r < R; r += kWG) {
-            const int q0 = rp[b.r0 + r] - p0, q1 = rp[b.r0 + r + 1] - p0;
+            const int q1 = s_rp[r + 1];
             Acc s = (Acc)0;
-            for (int q = q0; q < q1; ++q) s += s_prod[q];
+            for (int q = s_rp[r]; q < q1; ++q) s += s_prod[q];
             epi(b.r0 + r, s);
         }
     }
