@@ -329,6 +329,9 @@ int pdhg_unrolled_forward(pdhg_ctx *ctx, int K, int ckpt_every,
  * depend on ckpt_every.  The projection's subgradient is 0 at a tie. */
 int pdhg_unrolled_backward(pdhg_tape *tape, const double *gxK, double *gc,
                            double *gb, double *gAval, int mem);
+/* Release a tape.  pdhg_destroy releases the device memory of the tapes of
+ * its context; their handles must still be passed to pdhg_tape_free, and
+ * pdhg_unrolled_backward on them returns PDHG_E_STATE. */
 void pdhg_tape_free(pdhg_tape *tape);
 
 /* ---- kernels for checking and measurement ------------------------------ */

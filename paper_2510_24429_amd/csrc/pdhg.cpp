@@ -159,6 +159,9 @@ struct pdhg_ctx {
     hipGraphExec_t graph = nullptr;
     std::vector<const void *> graph_key;
 
+    // live adjoint tapes (detached when the context is destroyed)
+    std::vector<pdhg_tape *> tapes;
+
     // profiling
     bool profile = false;
     std::vector<ProfRec> prof;
@@ -929,11 +932,20 @@ int pdhg_create(int device, void *hip_stream, pdhg_ctx **out) {
     return PDHG_OK;
 }
 
+static void tape_release(pdhg_tape *tp);
+
 void pdhg_destroy(pdhg_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    // tapes still held by the caller lose their device memory and their
+    // context; pdhg_tape_free then only releases the handle
+    for (pdhg_tape *tp : c->tapes) {
+        tape_release(tp);
+        tp->ctx = nullptr;
+    }
+    c->tapes.clear();
     if (c->cb_thread.joinable()) {
         {
             std::lock_guard<std::mutex> lk(c->cb_mu);
@@ -1778,6 +1790,7 @@ int pdhg_unrolled_forward(pdhg_ctx *c, int K, int ckpt_every, int precision,
         pdhg_tape_free(tp);
         throw;
     }
+    c->tapes.push_back(tp);
     *tape = tp;
     return PDHG_OK;
     API_END(c)
@@ -1785,7 +1798,8 @@ int pdhg_unrolled_forward(pdhg_ctx *c, int K, int ckpt_every, int precision,
 
 int pdhg_unrolled_backward(pdhg_tape *tp, const double *gxK, double *gc,
                            double *gb, double *gAval, int mem) {
-    if (!tp || !tp->ctx) return PDHG_E_ARG;
+    if (!tp) return PDHG_E_ARG;
+    if (!tp->ctx) return PDHG_E_STATE;      // its context was destroyed
     pdhg_ctx *c = tp->ctx;
     API_BEGIN(c)
     if (!gxK || !gc || !gb || !gAval) return fail(c, PDHG_E_ARG, "null argument");
@@ -1797,14 +1811,30 @@ int pdhg_unrolled_backward(pdhg_tape *tp, const double *gxK, double *gc,
     API_END(c)
 }
 
-void pdhg_tape_free(pdhg_tape *tp) {
-    if (!tp) return;
-    if (tp->ctx) (void)hipSetDevice(tp->ctx->device);
-    if (tp->ctx && tp->ctx->stream) (void)hipStreamSynchronize(tp->ctx->stream);
+static void tape_release(pdhg_tape *tp) {
+    if (tp->ctx) {
+        (void)hipSetDevice(tp->ctx->device);
+        if (tp->ctx->stream) (void)hipStreamSynchronize(tp->ctx->stream);
+    }
     if (tp->ckx) (void)hipFree(tp->ckx);
     if (tp->cky) (void)hipFree(tp->cky);
     if (tp->ckax) (void)hipFree(tp->ckax);
     if (tp->st) (void)hipFree(tp->st);
+    tp->ckx = tp->cky = tp->ckax = nullptr;
+    tp->st = nullptr;
+}
+
+void pdhg_tape_free(pdhg_tape *tp) {
+    if (!tp) return;
+    if (tp->ctx) {
+        auto &v = tp->ctx->tapes;
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i] == tp) {
+                v.erase(v.begin() + (long)i);
+                break;
+            }
+    }
+    tape_release(tp);
     delete tp;
 }
 

@@ -96,6 +96,7 @@ class Solver:
                                    *[a.ptr for a in args], mem), self.ctx)
         self._keep = None
         self._cb = None
+        self._tapes = []
 
     @classmethod
     def from_lp(cls, lp, lb=None, **kw) -> "Solver":
@@ -104,6 +105,11 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None):
+            for ref in getattr(self, "_tapes", []):
+                t = ref()
+                if t is not None:
+                    t.free()
+            self._tapes = []
             self.lib.pdhg_destroy(self.ctx)
             self.ctx = None
 
@@ -278,7 +284,11 @@ class Solver:
         L.check(self.lib.pdhg_unrolled_forward(self.ctx, K, ckpt_every, precision,
                                                tau, sigma, ax.ptr, ay.ptr, pK, mem,
                                                C.byref(tape)), self.ctx)
-        return xK, Tape(self, tape)
+        t = Tape(self, tape)
+        import weakref
+        self._tapes = [r for r in self._tapes if r() is not None]
+        self._tapes.append(weakref.ref(t))
+        return xK, t
 
 
 class Tape:
@@ -288,6 +298,8 @@ class Tape:
 
     def backward(self, gxK, device: bool = False):
         s = self.solver
+        if s is None or not self.h or not s.ctx:
+            raise L.PDHGError(-6, "tape was freed or its solver closed")
         a = _Arg(gxK, np.float64, s.n, "gxK")
         dev = a.mem == L.MEM_DEVICE
         gc, pc, mem = s._out(s.n, dev)
@@ -300,6 +312,7 @@ class Tape:
         if self.h:
             self.solver.lib.pdhg_tape_free(self.h)
             self.h = None
+        self.solver = None
 
     def __del__(self):
         try:

@@ -173,3 +173,17 @@ def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
         assert max(errs) <= 1e-6, (group, max(errs))
     fwd_gpu(lp.c, lp.b, lp.a_v)
     s.close()
+
+
+def test_tape_outliving_its_solver_is_released_cleanly(Solver, oracle):
+    # regression: a tape freed after its context was destroyed must not touch
+    # the destroyed context
+    from paper_2510_24429_amd._lib import PDHGError
+    lp = lpgen.planted_uniform(m=100, n=200, k=4, seed=43)
+    s = Solver.from_lp(lp)
+    s.configure(ruiz_passes=10, power_iters=5)
+    xK, tape = s.unrolled_forward(10, 5, 0.1, 0.1)
+    s.close()
+    with pytest.raises(PDHGError):
+        tape.backward(np.ones(lp.n))
+    tape.free()
