@@ -288,6 +288,36 @@ int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
                                           const pdhg_snapshot_info *info),
                                void *user);
 
+/* ---- Algorithm 1: concurrent crossover ---------------------------------- */
+
+/* A crossover routine supplied by the caller (the paper's CPU crossover, which
+ * this library does not implement).  Called on a library thread with a
+ * snapshot's unscaled x (n), y (m), z (n) (valid for the duration of the
+ * call) and `cancel`, which becomes nonzero once another thread has won; the
+ * routine should poll it and return promptly.  Returns 1 if it found a basic
+ * optimal solution, 0 otherwise.  idx is the snapshot index, or -1 for the
+ * final iterate. */
+typedef int (*pdhg_crossover_fn)(void *user, int idx,
+                                 const pdhg_snapshot_info *info,
+                                 const double *x, const double *y,
+                                 const double *z,
+                                 const volatile int32_t *cancel);
+
+/* Concurrent crossover PDHG (Algorithm 1, Section 3.1): iterate; every
+ * snapshot the configured levels emit (for the paper's schedule, configure
+ * with pdhg_alg1_levels(eps_cross, eps_rel)) launches `fn` on a new host
+ * thread, at most max_threads at a time (a later snapshot waits for a free
+ * thread; 0 means no limit).  The first call to return 1 wins: the others see
+ * *cancel set, PDHG is stopped, and *winner receives its index.  When PDHG
+ * reaches eps_rel without a winner, `fn` also runs on the calling thread from
+ * the final iterate (idx -1) unless a snapshot was taken from that same
+ * iterate.  *winner is -2 if no call succeeded.  *status receives the PDHG
+ * status (PDHG_CANCELLED when a crossover won first).  Returns after every
+ * crossover thread has finished. */
+int pdhg_concurrent_crossover(pdhg_ctx *ctx, pdhg_crossover_fn fn, void *user,
+                              int max_threads, int64_t max_iters,
+                              int *winner, int *status);
+
 /* ---- FP32 bulk iteration with FP64 refinement --------------------------- */
 
 /* Iterative refinement: round 0 solves the LP with the bulk iteration in

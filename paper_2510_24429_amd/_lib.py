@@ -100,6 +100,9 @@ class KernelTime(C.Structure):
 
 
 SNAP_CB = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.POINTER(SnapInfo))
+CROSSOVER_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(SnapInfo),
+                           C.POINTER(C.c_double), C.POINTER(C.c_double),
+                           C.POINTER(C.c_double), C.POINTER(C.c_int32))
 
 vp = C.c_void_p
 i64 = C.c_int64
@@ -134,6 +137,8 @@ SIGNATURES = {
     "pdhg_snapshot_count": (i32, [vp, C.POINTER(i32)]),
     "pdhg_snapshot": (i32, [vp, i32, C.POINTER(SnapInfo), vp, vp, vp, i32]),
     "pdhg_set_snapshot_callback": (i32, [vp, SNAP_CB, vp]),
+    "pdhg_concurrent_crossover": (i32, [vp, CROSSOVER_FN, vp, i32, i64,
+                                        C.POINTER(i32), C.POINTER(i32)]),
     "pdhg_solve_refined": (i32, [vp, C.POINTER(RefineParams),
                                  C.POINTER(RefineInfo)]),
     "pdhg_refine_log": (i32, [vp, vp, i32, C.POINTER(i32)]),

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -1392,6 +1393,109 @@ int pdhg_kernel_times(pdhg_ctx *c, pdhg_kernel_time *out, int cap, int *count,
         c->prof_launch[0] = c->prof_launch[1] = 0;
         c->prof_ms[0] = c->prof_ms[1] = 0;
     }
+    return PDHG_OK;
+    API_END(c)
+}
+
+// ------------------------------------------------------------ Algorithm 1
+
+int pdhg_concurrent_crossover(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
+                              int max_threads, int64_t max_iters, int *winner,
+                              int *status) {
+    API_BEGIN(c)
+    if (!fn || max_threads < 0 || max_iters < 0)
+        return fail(c, PDHG_E_ARG, "bad argument to pdhg_concurrent_crossover");
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    struct Job {
+        int idx;
+        pdhg_snapshot_info info;
+        std::vector<double> x, y, z;
+    };
+    volatile int32_t cancel = 0;
+    std::atomic<int> win{-2};
+    std::atomic<int> running{0};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<std::thread> threads;
+    auto run_job = [&](std::shared_ptr<Job> j) {
+        const int ok = fn(user, j->idx, &j->info, j->x.data(), j->y.data(),
+                          j->z.data(), &cancel);
+        if (ok == 1) {
+            int expected = -2;
+            if (win.compare_exchange_strong(expected, j->idx)) {
+                cancel = 1;
+                c->cancel_flag.store(1);
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            running.fetch_sub(1);
+        }
+        cv.notify_all();
+    };
+    auto fetch = [&](int idx) {
+        auto j = std::make_shared<Job>();
+        j->idx = idx;
+        j->x.resize((size_t)c->n);
+        j->y.resize((size_t)c->m);
+        j->z.resize((size_t)c->n);
+        if (idx >= 0) {
+            const SnapMeta &sm = c->snaps[idx];
+            j->info = sm.info;
+            const double *base = c->slots + (int64_t)sm.slot * (2 * c->n + c->m);
+            HIPC(hipMemcpyAsync(j->x.data(), base, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipMemcpyAsync(j->y.data(), base + c->n, c->m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipMemcpyAsync(j->z.data(), base + c->n + c->m, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+        }
+        return j;
+    };
+    auto launch = [&](std::shared_ptr<Job> j) {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] {
+            return max_threads == 0 || running.load() < max_threads || cancel;
+        });
+        if (cancel) return;
+        running.fetch_add(1);
+        threads.emplace_back(run_job, j);
+    };
+    int st = c->status;
+    size_t launched = 0;
+    const int64_t target = std::min<int64_t>(c->k_host + max_iters, c->params.max_iters);
+    try {
+        for (;;) {
+            // snapshots emitted so far (including the k = 0 check)
+            if (!c->initial_done) run_iterations(c, 0, target);
+            while (launched < c->snaps.size() && !cancel) {
+                launch(fetch((int)launched));
+                ++launched;
+            }
+            st = c->status;
+            if (st != PDHG_RUNNING || cancel || c->k_host >= target) break;
+            run_iterations(c, c->params.eval_every, target);
+        }
+        // Algorithm 1's last line: crossover from the converged iterate on
+        // this thread, unless that iterate was already handed out
+        if (!cancel && st == PDHG_CONVERGED &&
+            (c->snaps.empty() || c->snaps.back().info.iter != c->k_host)) {
+            auto j = fetch(-1);
+            pdhg_get_iterate(c, j->x.data(), j->y.data(), j->z.data(), PDHG_MEM_HOST);
+            std::memset(&j->info, 0, sizeof j->info);
+            j->info.level = c->params.eps_rel;
+            j->info.iter = c->k_host;
+            j->info.t_wall = now_s() - c->t_start;
+            running.fetch_add(1);
+            run_job(j);
+        }
+    } catch (...) {
+        cancel = 1;
+        for (auto &t : threads) t.join();
+        throw;
+    }
+    for (auto &t : threads) t.join();
+    c->cancel_flag.store(0);
+    if (winner) *winner = win.load();
+    if (status) *status = st;
     return PDHG_OK;
     API_END(c)
 }

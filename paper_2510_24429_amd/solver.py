@@ -223,6 +223,33 @@ class Solver:
         self._cb = L.SNAP_CB(_cb)
         L.check(self.lib.pdhg_set_snapshot_callback(self.ctx, self._cb, None), self.ctx)
 
+    # ------------------------------------------------------------- Algorithm 1
+    def concurrent_crossover(self, fn, max_threads: int = 0,
+                             max_iters: int = 2 ** 62):
+        """Algorithm 1: fn(idx, info, x, y, z, cancelled) -> bool runs on a
+        library thread for every snapshot (idx -1: the converged iterate);
+        x, y, z are numpy views valid during the call, cancelled() tells
+        whether another call has already won.  Returns (winner, status)."""
+        n, m = self.n, self.m
+
+        def _fn(user, idx, info, px, py, pz, pcancel):
+            x = np.ctypeslib.as_array(px, shape=(n,))
+            y = np.ctypeslib.as_array(py, shape=(m,))
+            z = np.ctypeslib.as_array(pz, shape=(n,))
+            try:
+                ok = fn(idx, info.contents.asdict(), x, y, z,
+                        lambda: pcancel[0] != 0)
+            except Exception:
+                ok = False
+            return 1 if ok else 0
+
+        cb = L.CROSSOVER_FN(_fn)
+        win, st = C.c_int(0), C.c_int(0)
+        L.check(self.lib.pdhg_concurrent_crossover(self.ctx, cb, None, max_threads,
+                                                   int(max_iters), C.byref(win),
+                                                   C.byref(st)), self.ctx)
+        return win.value, st.value
+
     # ------------------------------------------------------------- refinement
     def solve_refined(self, **kw) -> dict:
         rp = L.RefineParams()

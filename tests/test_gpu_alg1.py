@@ -1,0 +1,71 @@
+"""Algorithm 1 (Section 3.1) concurrent crossover harness on the GPU, with a
+stand-in crossover routine (the simplex crossover itself is external)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2510_24429_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2510_24429_amd.solver import Solver as S
+    return S
+
+
+def test_first_successful_crossover_wins_and_cancels(Solver, oracle):
+    lp = lpgen.planted_uniform(m=20000, n=60000, k=5, seed=4)
+    levels = oracle.alg1_levels(1e-2, 1e-10)
+    calls, lock = [], threading.Lock()
+
+    def crossover(idx, info, x, y, z, cancelled):
+        # stand-in: a start looser than 1e-4 never finishes (it runs until it
+        # is cancelled); one at 1e-4 or tighter finishes after 50 ms
+        with lock:
+            calls.append((idx, info["level"], info["maxresid"]))
+        assert np.all(z >= 0) and x.shape == (lp.n,) and y.shape == (lp.m,)
+        if info["level"] > 1e-4:
+            while not cancelled():
+                time.sleep(0.005)
+            return False
+        time.sleep(0.05)
+        return True
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-10, levels=levels)
+        t0 = time.time()
+        winner, status = s.concurrent_crossover(crossover)
+        dt = time.time() - t0
+        info = s.info()
+        snaps = [s.snapshot(i)[0] for i in range(s.snapshot_count())]
+    assert status == 4                          # PDHG stopped by the winner
+    assert snaps[winner]["level"] == 1e-4
+    assert info["kkt"]["maxresid"] > 1e-10      # it never reached eps_rel
+    assert sorted(c[1] for c in calls)[-1] == 1e-2   # earlier starts launched
+    assert all(c[2] <= c[1] for c in calls)
+    assert dt < 60
+
+
+def test_no_winner_runs_final_crossover_on_converged_iterate(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    seen = []
+
+    def crossover(idx, info, x, y, z, cancelled):
+        seen.append((idx, info["level"]))
+        if idx == -1:
+            kk = oracle.kkt(lp, x.copy(), y.copy())
+            assert kk["maxresid"] <= 1e-6
+        return False
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-6, levels=[1e-2, 1e-4])     # eps_rel not a level
+        winner, status = s.concurrent_crossover(crossover, max_threads=1)
+    assert winner == -2 and status == 1
+    assert sorted(seen)[0] == (-1, 1e-6)
+    assert sorted(l for i, l in seen if i >= 0) == [1e-4, 1e-2]
