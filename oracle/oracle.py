@@ -35,10 +35,12 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("ruiz_passes", C.c_int32), ("power_iters", C.c_int32),
                 ("eval_every", C.c_int32), ("literal_snapshots", C.c_int32),
+                ("variant", C.c_int32), ("pad0_", C.c_int32),
                 ("eps_rel", C.c_double), ("eta", C.c_double),
                 ("omega0", C.c_double), ("eta_factor", C.c_double),
                 ("beta_suff", C.c_double), ("beta_nec", C.c_double),
                 ("beta_art", C.c_double), ("omega_theta", C.c_double),
+                ("reflect", C.c_double),
                 ("max_iters", C.c_int64), ("time_limit_s", C.c_double),
                 ("n_levels", C.c_int32), ("pad_", C.c_int32),
                 ("levels", C.POINTER(C.c_double))]
@@ -99,16 +101,17 @@ def _csr(lp):
 
 
 DEFAULTS = dict(ruiz_passes=10, power_iters=100, eval_every=64,
-                literal_snapshots=0, eps_rel=1e-6, eta=0.0, omega0=0.0,
-                eta_factor=0.9, beta_suff=0.2, beta_nec=0.8, beta_art=0.36,
-                omega_theta=0.5, max_iters=10**9, time_limit_s=3600.0)
+                literal_snapshots=0, variant=0, eps_rel=1e-6, eta=0.0,
+                omega0=0.0, eta_factor=0.9, beta_suff=0.2, beta_nec=0.8,
+                beta_art=0.36, omega_theta=0.5, reflect=1.0, max_iters=10**9,
+                time_limit_s=3600.0)
 
 
 def make_params(levels: Sequence[float] = (), **kw) -> tuple:
     d = dict(DEFAULTS)
     d.update(kw)
     lv = np.ascontiguousarray(np.asarray(levels, dtype=np.float64))
-    p = Params(**{k: d[k] for k in DEFAULTS}, n_levels=len(lv), pad_=0,
+    p = Params(**{k: d[k] for k in DEFAULTS}, pad0_=0, n_levels=len(lv), pad_=0,
                levels=lv.ctypes.data_as(C.POINTER(C.c_double)))
     return p, lv
 

@@ -48,11 +48,14 @@ typedef struct {
     int32_t power_iters;        /* power-iteration steps (100) */
     int32_t eval_every;         /* iterations between evaluations (64) */
     int32_t literal_snapshots;  /* 1: one snapshot level per evaluation */
+    int32_t variant;            /* 0 averaged (PDLP-style), 1 reflected Halpern */
+    int32_t pad0_;
     double eps_rel;             /* termination tolerance on maxresid */
     double eta;                 /* step size; <= 0: 0.9 / sigma_hat */
     double omega0;              /* primal weight; <= 0: ||c~|| / ||b~|| */
     double eta_factor;          /* 0.9 */
     double beta_suff, beta_nec, beta_art, omega_theta;  /* 0.2 0.8 0.36 0.5 */
+    double reflect;             /* Halpern reflection rho (1) */
     int64_t max_iters;
     double time_limit_s;
     int32_t n_levels;
@@ -404,6 +407,237 @@ static int outer_reached(const or_pattern *A, const double *v,
     return K.maxresid <= o->target;
 }
 
+/*
+ * Reflected Halpern PDHG with restarts (the variant the cuPDLP+ line of work
+ * uses; the paper's solver follows it per Section 4.1 but states no details).
+ * With T(z) the PDHG step of the averaged variant applied to z = (x, y),
+ *   z <- lambda ((1 + rho) T(z) - rho z) + (1 - lambda) z_0,
+ *   lambda = (t + 1) / (t + 2), t = steps since the last restart (0 first),
+ * anchored at the restart point z_0.  The Halpern iterate z itself is not
+ * projected (it may leave x >= l), so every eval_every steps (and at k = 0)
+ * the candidate for Algorithm 1's test, the eps_rel stop and the returned
+ * solution is T(z), which is; z's own KKT is only logged.  Restarts test the
+ * fixed-point residual r(z) = sqrt(omega ||x - T_x(z)||^2 +
+ * ||y - T_y(z)||^2 / omega) against the value at the last restart (reading:
+ * taken as r of the iterate the restart started from, re-weighted with the
+ * new omega) and the previous check, with the same thresholds as the averaged
+ * variant, and restart at T(z) with the same primal-weight update.
+ */
+static void pdhg_step(const or_pattern *A, const double *vs, const double *bs,
+                      const double *cs, const double *ls, double tau,
+                      double sigma, const double *xs, const double *ys,
+                      double *xh, double *yh, double *wm, double *wn,
+                      double *xe) {
+    int64_t m = A->m, n = A->n;
+    at_times(A, vs, ys, wn);
+    for (int64_t j = 0; j < n; ++j) {
+        double vj = xs[j] - tau * (cs[j] - wn[j]);
+        xh[j] = vj < ls[j] ? ls[j] : vj;
+    }
+    for (int64_t j = 0; j < n; ++j) xe[j] = 2.0 * xh[j] - xs[j];
+    a_times(A, vs, xe, wm);
+    for (int64_t i = 0; i < m; ++i) yh[i] = ys[i] + sigma * (bs[i] - wm[i]);
+}
+
+static int outer_reached(const or_pattern *A, const double *v,
+                         const double *dr, const double *dc,
+                         const double *xs, const double *ys,
+                         const outer_t *o);
+
+static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
+             const int32_t *ci, const double *v, const double *b,
+             const double *c, const double *l, const double *x0,
+             const double *y0, const or_params *prm, or_info *info,
+             double *x_out, double *y_out, double *z_out, or_snap *snaps,
+             double *snap_x, double *snap_y, double *snap_z, int32_t trace_k,
+             double *trace_x, double *trace_y, int32_t log_cap,
+             double *eval_log, const outer_t *outer) {
+    double t0 = now_s();
+    or_pattern A = {m, n, rp, ci};
+    int64_t nnz = rp[m];
+    for (int j = 1; j < prm->n_levels; ++j)
+        if (!(prm->levels[j] < prm->levels[j - 1])) return -1;
+    if (prm->eval_every < 1) return -1;
+    double *vs = dalloc(nnz), *dr = dalloc(m), *dc = dalloc(n);
+    double *bs = dalloc(m), *cs = dalloc(n), *ls = dalloc(n);
+    double *xs = dalloc(n), *ys = dalloc(m), *xh = dalloc(n), *yh = dalloc(m);
+    double *xe = dalloc(n), *xa = dalloc(n), *ya = dalloc(m);  /* anchor */
+    double *wm = dalloc(m), *wn = dalloc(n), *wm2 = dalloc(m),
+           *wn2 = dalloc(n), *xu = dalloc(n), *yu = dalloc(m);
+    double *zero_l = dalloc(n);
+    or_ruiz(m, n, rp, ci, v, prm->ruiz_passes, dr, dc, vs);
+    const double *lv = l ? l : zero_l;
+    for (int64_t i = 0; i < m; ++i) bs[i] = dr[i] * b[i];
+    for (int64_t j = 0; j < n; ++j) cs[j] = dc[j] * c[j];
+    for (int64_t j = 0; j < n; ++j) ls[j] = lv[j] / dc[j];
+    double sigma_hat = 0.0, eta;
+    if (prm->eta > 0.0) {
+        eta = prm->eta;
+    } else {
+        sigma_hat = or_power(m, n, rp, ci, vs, prm->power_iters);
+        eta = prm->eta_factor / sigma_hat;
+    }
+    double nbs = nrm2(bs, m), ncs = nrm2(cs, n), omega;
+    if (prm->omega0 > 0.0)
+        omega = prm->omega0;
+    else
+        omega = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
+    const double omega0 = omega, rho = prm->reflect;
+    double tau = eta / omega, sigma = eta * omega;
+    prob_t P = {A, v, vs, b, c, lv, bs, cs, ls, dr, dc, nrm2(b, m), nrm2(c, n),
+                wm2, wn2, wm2, wn2, xu, yu};
+    /* eval_cand uses wm/wn (first pair) as scratch too: give it its own */
+    P.wm = dalloc(m);
+    P.wn = dalloc(n);
+    for (int64_t j = 0; j < n; ++j) xs[j] = x0 ? x0[j] / dc[j] : 0.0;
+    for (int64_t i = 0; i < m; ++i) ys[i] = y0 ? y0[i] / dr[i] : 0.0;
+    memcpy(xa, xs, (size_t)n * sizeof(double));
+    memcpy(ya, ys, (size_t)m * sizeof(double));
+    double t1 = now_s();
+    int status = OR_RUNNING, restarts = 0, n_snap = 0, next_level = 0;
+    int returned = 0, n_log = 0;
+    int64_t k = 0, t = 0;
+    double r_last = INFINITY, r_prev = INFINITY;
+    cand_t Sc, Sh;
+    or_kkt_t final_kkt;
+    memset(&final_kkt, 0, sizeof final_kkt);
+    for (;;) {
+        if (k % prm->eval_every == 0) {
+            /* both candidates: z and T(z) */
+            pdhg_step(&A, vs, bs, cs, ls, tau, sigma, xs, ys, xh, yh, wm, wn, xe);
+            eval_cand(&P, xs, ys, xa, ya, &Sc);
+            eval_cand(&P, xh, yh, xa, ya, &Sh);
+            double fx = 0.0, fy = 0.0;
+            for (int64_t j = 0; j < n; ++j) fx += (xs[j] - xh[j]) * (xs[j] - xh[j]);
+            for (int64_t i = 0; i < m; ++i) fy += (ys[i] - yh[i]) * (ys[i] - yh[i]);
+            const double r_cur = sqrt(omega * fx + fy / omega);
+            const int bi = 1;
+            const cand_t *best = &Sh;
+            int restarted = 0;
+            if (!Sc.finite || !Sh.finite || !isfinite(r_cur)) {
+                status = OR_NUMERICAL;
+            } else {
+                while (next_level < prm->n_levels &&
+                       best->kkt.maxresid <= prm->levels[next_level]) {
+                    snaps[n_snap].level = prm->levels[next_level];
+                    snaps[n_snap].iter = k;
+                    snaps[n_snap].maxresid = best->kkt.maxresid;
+                    snaps[n_snap].candidate = bi;
+                    if (snap_x)
+                        write_unscaled(&P, bi ? xh : xs, bi ? yh : ys,
+                                       snap_x + (int64_t)n_snap * n,
+                                       snap_y + (int64_t)n_snap * m,
+                                       snap_z + (int64_t)n_snap * n);
+                    ++n_snap; ++next_level;
+                    if (prm->literal_snapshots) break;
+                }
+                if (best->kkt.maxresid <= prm->eps_rel) {
+                    status = OR_CONVERGED;
+                    returned = bi;
+                    final_kkt = best->kkt;
+                    if (bi) {
+                        memcpy(xs, xh, (size_t)n * sizeof(double));
+                        memcpy(ys, yh, (size_t)m * sizeof(double));
+                    }
+                } else if (k == 0) {
+                    r_last = r_cur;
+                } else {
+                    const int r = (r_cur <= prm->beta_suff * r_last) ||
+                                  (r_cur <= prm->beta_nec * r_last && r_cur > r_prev) ||
+                                  ((double)t >= prm->beta_art * (double)k);
+                    if (r) {
+                        const double dx = sqrt(Sh.dx2), dy = sqrt(Sh.dy2);
+                        if (dx > 1e-10 && dy > 1e-10)
+                            omega = exp(prm->omega_theta * log(dy / dx) +
+                                        (1.0 - prm->omega_theta) * log(omega));
+                        tau = eta / omega;
+                        sigma = eta * omega;
+                        memcpy(xs, xh, (size_t)n * sizeof(double));
+                        memcpy(ys, yh, (size_t)m * sizeof(double));
+                        memcpy(xa, xh, (size_t)n * sizeof(double));
+                        memcpy(ya, yh, (size_t)m * sizeof(double));
+                        t = 0;
+                        r_last = sqrt(omega * fx + fy / omega);
+                        r_prev = INFINITY;
+                        ++restarts;
+                        restarted = 1;
+                    } else {
+                        r_prev = r_cur;
+                    }
+                }
+            }
+            if (eval_log && n_log < log_cap) {
+                double *e = eval_log + 8 * (int64_t)n_log++;
+                e[0] = (double)k; e[1] = Sc.kkt.maxresid; e[2] = Sh.kkt.maxresid;
+                e[3] = r_cur; e[4] = r_last; e[5] = (double)restarted;
+                e[6] = 1.0; e[7] = omega;
+            }
+            if (status == OR_RUNNING && outer && !restarted &&
+                outer_reached(&A, v, dr, dc, xh, yh, outer)) {
+                status = OR_CONVERGED;
+                returned = 1;
+                final_kkt = Sh.kkt;
+                memcpy(xs, xh, (size_t)n * sizeof(double));
+                memcpy(ys, yh, (size_t)m * sizeof(double));
+            } else if (status == OR_RUNNING && outer && restarted &&
+                       outer_reached(&A, v, dr, dc, xs, ys, outer)) {
+                /* after a restart the current iterate already is T(z) */
+                status = OR_CONVERGED;
+                returned = 1;
+                final_kkt = Sh.kkt;
+            }
+            if (status == OR_RUNNING && prm->time_limit_s > 0.0 &&
+                now_s() - t0 > prm->time_limit_s)
+                status = OR_TIME_LIMIT;
+        }
+        /* trace: the iterate after step k and the evaluation due at k */
+        if (k >= 1 && k <= trace_k && trace_x) {
+            for (int64_t j = 0; j < n; ++j) trace_x[(k - 1) * n + j] = dc[j] * xs[j];
+            for (int64_t i = 0; i < m; ++i) trace_y[(k - 1) * m + i] = dr[i] * ys[i];
+        }
+        if (status != OR_RUNNING) break;
+        if (k >= prm->max_iters) { status = OR_ITER_LIMIT; break; }
+        /* one reflected Halpern step */
+        pdhg_step(&A, vs, bs, cs, ls, tau, sigma, xs, ys, xh, yh, wm, wn, xe);
+        const double lam = (double)(t + 1) / (double)(t + 2);
+        for (int64_t j = 0; j < n; ++j)
+            xs[j] = lam * ((1.0 + rho) * xh[j] - rho * xs[j]) + (1.0 - lam) * xa[j];
+        for (int64_t i = 0; i < m; ++i)
+            ys[i] = lam * ((1.0 + rho) * yh[i] - rho * ys[i]) + (1.0 - lam) * ya[i];
+        ++k; ++t;
+    }
+    double t2 = now_s();
+    if (status != OR_CONVERGED) {
+        cand_t S;
+        eval_cand(&P, xs, ys, xa, ya, &S);
+        final_kkt = S.kkt;
+        returned = 0;
+    }
+    write_unscaled(&P, xs, ys, x_out, y_out, z_out);
+    if (info) {
+        info->status = status;
+        info->candidate = returned;
+        info->iters = k;
+        info->restarts = restarts;
+        info->n_snap = n_snap;
+        info->n_log = n_log;
+        info->sigma_hat = sigma_hat;
+        info->eta = eta;
+        info->omega0 = omega0;
+        info->omega = omega;
+        info->tau = tau;
+        info->sigma = sigma;
+        info->t_setup = t1 - t0;
+        info->t_iter = t2 - t1;
+        info->kkt = final_kkt;
+    }
+    free(vs); free(dr); free(dc); free(bs); free(cs); free(ls); free(xs);
+    free(ys); free(xh); free(yh); free(xe); free(xa); free(ya); free(wm);
+    free(wn); free(wm2); free(wn2); free(xu); free(yu); free(zero_l);
+    free(P.wm); free(P.wn);
+    return 0;
+}
+
 static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
              const int32_t *ci, const double *v, const double *b,
              const double *c, const double *l, const double *x0,
@@ -412,6 +646,11 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
              double *snap_x, double *snap_y, double *snap_z, int32_t trace_k,
              double *trace_x, double *trace_y, int32_t log_cap,
              double *eval_log, const outer_t *outer) {
+    if (prm->variant == 1)
+        return solve_halpern(m, n, rp, ci, v, b, c, l, x0, y0, prm, info,
+                             x_out, y_out, z_out, snaps, snap_x, snap_y,
+                             snap_z, trace_k, trace_x, trace_y, log_cap,
+                             eval_log, outer);
     double t0 = now_s();
     or_pattern A = {m, n, rp, ci};
     int64_t nnz = rp[m];

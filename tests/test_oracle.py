@@ -24,15 +24,17 @@ def _dense_lp(A, b, c, name="dense"):
 
 # ---------------------------------------------------------------- brute force
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("seed", range(8))
 @pytest.mark.parametrize("shape", [(2, 4), (3, 6), (4, 8)])
-def test_optimum_matches_vertex_enumeration(oracle, seed, shape):
+def test_optimum_matches_vertex_enumeration(oracle, seed, shape, variant):
     m, n = shape
     lp = lpgen.tiny_dense(m, n, seed=100 * m + seed)
     A = lp.dense()
     p, d, pv, dv = lp_optimum(A, lp.b, lp.c)
     assert abs(p - d) <= 1e-9 * (1 + abs(p))          # strong duality
-    r = oracle.solve(lp, eps_rel=1e-10, eval_every=16, max_iters=2_000_000)
+    r = oracle.solve(lp, eps_rel=1e-10, eval_every=16, max_iters=2_000_000,
+                     variant=variant)
     assert r.info["status"] == 1
     assert abs(r.kkt["pobj"] - p) <= 1e-8 * (1 + abs(p))
     assert abs(r.kkt["dobj"] - d) <= 1e-8 * (1 + abs(d))
@@ -42,19 +44,21 @@ def test_optimum_matches_vertex_enumeration(oracle, seed, shape):
             assert lp.b @ y <= lp.c @ x + 1e-9
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("seed", range(4))
-def test_planted_optimum_value(oracle, seed):
+def test_planted_optimum_value(oracle, seed, variant):
     lp = lpgen.planted_uniform(m=60, n=120, k=4, seed=seed)
     pstar = lp.c @ lp.x_star
     assert abs(pstar - lp.b @ lp.y_star) <= 1e-10 * (1 + abs(pstar))
-    r = oracle.solve(lp, eps_rel=1e-9)
+    r = oracle.solve(lp, eps_rel=1e-9, variant=variant)
     assert r.info["status"] == 1
     assert abs(r.kkt["pobj"] - pstar) <= 1e-7 * (1 + abs(pstar))
 
 
 # ---------------------------------------------------------------- closed forms
 
-def test_one_row_lp_closed_form(oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_one_row_lp_closed_form(oracle, variant):
     # min c^T x s.t. a^T x = beta, x >= 0 with a > 0: p* = beta * min c_j / a_j
     rng = np.random.default_rng(7)
     n = 9
@@ -62,7 +66,7 @@ def test_one_row_lp_closed_form(oracle):
     c = rng.uniform(1.0, 3.0, n)
     beta = 2.5
     lp = _dense_lp(a[None, :], np.array([beta]), c)
-    r = oracle.solve(lp, eps_rel=1e-11, eval_every=8)
+    r = oracle.solve(lp, eps_rel=1e-11, eval_every=8, variant=variant)
     pstar = beta * np.min(c / a)
     assert r.info["status"] == 1
     assert abs(r.kkt["pobj"] - pstar) <= 1e-9 * (1 + pstar)
@@ -70,14 +74,15 @@ def test_one_row_lp_closed_form(oracle):
     assert abs(r.x[j] - beta / a[j]) <= 1e-7
 
 
-def test_identity_matrix_closed_form(oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_identity_matrix_closed_form(oracle, variant):
     # A = I: the only feasible point is x = b, so p* = c^T b, y = c - z
     rng = np.random.default_rng(3)
     n = 12
     b = rng.uniform(0.1, 1.0, n)
     c = rng.standard_normal(n)
     lp = _dense_lp(np.eye(n), b, c)
-    r = oracle.solve(lp, eps_rel=1e-11, eval_every=4)
+    r = oracle.solve(lp, eps_rel=1e-11, eval_every=4, variant=variant)
     assert r.info["status"] == 1
     assert np.max(np.abs(r.x - b)) <= 1e-9
     assert abs(r.kkt["pobj"] - c @ b) <= 1e-9 * (1 + abs(c @ b))
@@ -114,18 +119,21 @@ def test_kkt_at_planted_point_and_perturbations(oracle):
 
 # ---------------------------------------------------------------- invariants
 
-def test_iterates_respect_bounds_and_gap_identity(oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_iterates_respect_bounds_and_gap_identity(oracle, variant):
     lp = lpgen.planted_uniform(m=80, n=160, k=5, seed=2)
     rng = np.random.default_rng(2)
     l = -rng.uniform(0.0, 0.5, lp.n)
     r = oracle.solve(lp, l=l, eps_rel=1e-30, max_iters=150, trace_k=150,
-                     eval_every=32)
+                     eval_every=32, variant=variant)
     A = lp.dense()
     for k in range(150):
         x, y = r.trace_x[k], r.trace_y[k]
         # projection is exact in the scaled space; unscaling D_c (l / D_c)
-        # may round l by an ulp
-        assert np.all(x >= l - 4.5e-16 * np.abs(l))
+        # may round l by an ulp.  (The Halpern iterate is a combination of
+        # projected and unprojected points and is not bound to x >= l.)
+        if variant == 0:
+            assert np.all(x >= l - 4.5e-16 * np.abs(l))
         # c^T x - b^T y - l^T z = z^T (x - l) - r_D^T x - y^T r_P   (any x, y)
         d = lp.c - A.T @ y
         z = np.maximum(0.0, d)
@@ -378,3 +386,41 @@ def test_adjoint_linearity_transpose(oracle):
         lhs = w @ jvp
         rhs = uc @ gc + ub @ gb
         assert abs(lhs - rhs) <= 1e-6 * (abs(lhs) + abs(rhs) + 1e-12)
+
+
+def test_halpern_first_step_is_the_pdhg_step(oracle):
+    # with reflection rho = 1 and lambda = 1/2 the first Halpern step from the
+    # anchor z0 gives z1 = (1/2)(2 T(z0) - z0) + (1/2) z0 = T(z0), i.e. the
+    # averaged variant's first iterate; rho = 0 gives the midpoint of z0 = 0
+    # and T(z0)
+    lp = lpgen.planted_uniform(m=40, n=90, k=4, seed=3)
+    a = oracle.solve(lp, eps_rel=1e-30, max_iters=1, trace_k=1, eval_every=50)
+    h = oracle.solve(lp, eps_rel=1e-30, max_iters=1, trace_k=1, eval_every=50,
+                     variant=1)
+    assert np.allclose(h.trace_x[0], a.trace_x[0], rtol=0, atol=1e-15)
+    assert np.allclose(h.trace_y[0], a.trace_y[0], rtol=0, atol=1e-15)
+    h0 = oracle.solve(lp, eps_rel=1e-30, max_iters=1, trace_k=1, eval_every=50,
+                      variant=1, reflect=0.0)
+    assert np.allclose(h0.trace_x[0], 0.5 * a.trace_x[0], rtol=0, atol=1e-15)
+
+
+def test_halpern_needs_fewer_iterations(oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    a = oracle.solve(lp, eps_rel=1e-8)
+    h = oracle.solve(lp, eps_rel=1e-8, variant=1)
+    assert a.info["status"] == h.info["status"] == 1
+    assert h.info["iters"] < a.info["iters"]
+    pstar = lp.c @ lp.x_star
+    assert abs(h.kkt["pobj"] - pstar) <= 1e-7 * (1 + abs(pstar))
+
+
+def test_halpern_returns_projected_point(oracle):
+    lp = lpgen.planted_uniform(m=80, n=160, k=5, seed=2)
+    rng = np.random.default_rng(2)
+    l = -rng.uniform(0.0, 0.5, lp.n)
+    r = oracle.solve(lp, l=l, eps_rel=1e-8, variant=1,
+                     levels=[1e-3, 1e-5, 1e-8], keep_snap_vectors=True)
+    assert r.info["status"] == 1
+    assert np.all(r.x >= l - 4.5e-16 * np.abs(l))
+    for i in range(len(r.snaps)):
+        assert np.all(r.snap_x[i] >= l - 4.5e-16 * np.abs(l))
