@@ -95,7 +95,9 @@ typedef struct {
     int64_t max_iters;          /* total iteration limit */
     double time_limit_s;        /* wall-clock limit per solve (3600) */
     int32_t use_graph;          /* replay eval_every-iteration batches as hipGraphs */
-    int32_t pad_;
+    int32_t variant;            /* 0: averaged iterates (PDLP-style restarts);
+                                   1: reflected Halpern iteration (cuPDLP+-style) */
+    double reflect;             /* Halpern reflection rho in [0, 1] (1) */
 } pdhg_params;
 
 /* Relative KKT errors of an unscaled iterate on the original data:
@@ -248,7 +250,12 @@ int pdhg_set_iterate(pdhg_ctx *ctx, const double *x, const double *y, int mem);
  * level >= the better candidate's maxresid (Algorithm 1's test), the solve
  * stops when it is <= eps_rel, and otherwise the adaptive restart rule runs.
  * Returns when the status leaves RUNNING or the iterations are done; *status
- * receives the pdhg_status. */
+ * receives the pdhg_status.
+ * With variant = 1 an iteration instead forms T(z) (the same fused steps) and
+ * z <- lambda((1 + rho)T(z) - rho z) + (1 - lambda) z_0, lambda = t/(t+1) for
+ * the t-th step since the restart point z_0; the evaluations use T(z) as the
+ * candidate (z itself is not projected), restarts test ||z - T(z)||_omega and
+ * restart at T(z), and a stopped solve reports T(z). */
 int pdhg_iterate(pdhg_ctx *ctx, int64_t max_iters, int *status);
 
 /* Ask a running pdhg_iterate / pdhg_solve_refined to stop at its next

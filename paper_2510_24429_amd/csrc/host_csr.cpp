@@ -41,6 +41,8 @@ extern "C" int pdhg_params_default(pdhg_params *p) {
     p->max_iters = (int64_t)1 << 62;
     p->time_limit_s = 3600.0;
     p->use_graph = 1;
+    p->variant = 0;
+    p->reflect = 1.0;
     return PDHG_OK;
 }
 

@@ -86,8 +86,11 @@ struct DevCsr {
 
 // Control state of a solve, resident on the device and written only by the
 // single-workgroup control kernel (and by the host between solves).
+// Per-candidate reduction quantities.  Q_FX2 / Q_FY2 are sums of squares of
+// the difference between the two candidates (||x - T_x(z)||^2 etc. for the
+// Halpern variant), accumulated under candidate 1.
 enum { Q_RP2, Q_RPMAX, Q_SRP2, Q_BY, Q_DY2, Q_RD2, Q_RDMAX, Q_SRD2, Q_CX,
-       Q_LZ, Q_DX2, Q_NQ };
+       Q_LZ, Q_DX2, Q_FX2, Q_FY2, Q_NQ };
 enum { S_RELP, S_RELD, S_RELG, S_MAXR, S_POBJ, S_DOBJ, S_NRP, S_NRD,
        S_RPINF, S_RDINF, S_SP2, S_SD2, S_SG, S_DX2, S_DY2, S_FIN, S_NS };
 
@@ -96,7 +99,8 @@ struct State {
     double K_last, K_prev;
     double nb, nc;                  // ||b||_2, ||c||_2 of the unscaled data
     double eps_rel, beta_suff, beta_nec, beta_art, omega_theta;
-    double pad_d;
+    double reflect;                 // Halpern reflection
+    double fx2, fy2;                // ||z - T(z)||^2 parts at the last evaluation
     long long k;                    // iterations done
     long long t_base;               // iterations since the last restart
     int status;
@@ -110,6 +114,7 @@ struct State {
     int returned_cand;
     int n_log, log_cap;
     int last_ncand;
+    int variant;                    // 0 averaged, 1 reflected Halpern
     double levels[kMaxLevels];
     double stats[2][S_NS];
     double snap_level[kMaxLevels];
@@ -124,6 +129,7 @@ struct Iter {
     T *x = nullptr, *y = nullptr, *xbar = nullptr, *ybar = nullptr;
     T *xl = nullptr, *yl = nullptr;       // last restart point
     T *ax = nullptr;                      // A~ x of the current iterate
+    T *ax0 = nullptr;                     // A~ x of the Halpern anchor
     T *cs = nullptr, *bs = nullptr, *ls = nullptr;   // scaled data in T
 };
 
@@ -142,6 +148,23 @@ void launch_primal(const DevCsr &At, const Iter<T> &v, bool has_l,
 template <typename T>
 void launch_dual(const DevCsr &A, const Iter<T> &v, bool avg,
                  const State *st, int off, hipStream_t s);
+// Halpern iteration: primal writes x^ = T_x(z) into v.xbar and the combined
+// x; dual gathers v.xbar and combines y and A~x with the anchors (xl, yl,
+// ax0).
+template <typename T>
+void launch_primal_halpern(const DevCsr &At, const Iter<T> &v, bool has_l,
+                           const State *st, int off, hipStream_t s);
+template <typename T>
+void launch_dual_halpern(const DevCsr &A, const Iter<T> &v, const State *st,
+                         int off, hipStream_t s);
+// Halpern evaluation: T(z) of the current iterate in FP64 arithmetic, into
+// v.xbar / v.ybar, with aty = A~^T y and axh = A~ x^ (FP64); axc is A~ x of
+// the current iterate (FP64).
+template <typename T>
+void launch_eval_T(const DevCsr &A, const DevCsr &At, const Iter<T> &v,
+                   bool has_l, const double *cs, const double *bs,
+                   const double *ls, const State *st, double *aty,
+                   double *axh, const double *axc, hipStream_t s);
 
 void launch_kkt_reduce(int ncand, const void *x0, const void *y0,
                        const void *x1, const void *y1, bool f32,
@@ -157,7 +180,7 @@ void launch_advance(State *st, int batch, hipStream_t s);
 void launch_set_status(State *st, int status, hipStream_t s);
 void launch_restart_apply(State *st, bool f32, void *x, void *y, void *ax,
                           void *xbar, void *ybar, const double *ax_avg,
-                          void *xl, void *yl, int64_t m, int64_t n,
+                          void *xl, void *yl, void *ax0, int64_t m, int64_t n,
                           hipStream_t s);
 void launch_snapshot_pack(const State *st, bool f32, const void *x0,
                           const void *y0, const void *x1, const void *y1,

@@ -175,6 +175,104 @@ struct DualEpi {
     }
 };
 
+// Reflected Halpern step, primal part over a row j of A~^T:
+//   x^_j = max(l_j, x_j - tau (c_j - g_j))   (kept for the dual part)
+//   x_j <- lambda ((1 + rho) x^_j - rho x_j) + (1 - lambda) x0_j
+// with lambda = t / (t + 1) for the t-th step since the anchor x0.
+template <typename T, bool HAS_L>
+struct PrimalHalpernEpi {
+    T *x, *xh;
+    const T *c, *l, *x0;
+    const State *st;
+    int off;
+    T tau, lam, rho;
+    __device__ __forceinline__ bool begin() {
+        if (st->status != PDHG_RUNNING) return false;
+        tau = (T)st->tau;
+        const double t = (double)(st->t_base + off + 1);
+        lam = (T)(t / (t + 1.0));
+        rho = (T)st->reflect;
+        return true;
+    }
+    __device__ __forceinline__ void operator()(int j, T g) const {
+        const T xj = x[j];
+        const T v = xj - tau * (c[j] - g);
+        const T lj = HAS_L ? l[j] : (T)0;
+        const T xhv = v < lj ? lj : v;
+        xh[j] = xhv;
+        x[j] = lam * (((T)1 + rho) * xhv - rho * xj) + ((T)1 - lam) * x0[j];
+    }
+};
+
+// Reflected Halpern step, dual part over a row i of A~ (q = (A~ x^)_i):
+//   y^_i = y_i + sigma (b_i - (2 q - (A~x)_i))
+//   y_i  <- lambda ((1 + rho) y^_i - rho y_i) + (1 - lambda) y0_i
+//   (A~x)_i <- lambda ((1 + rho) q - rho (A~x)_i) + (1 - lambda) (A~x0)_i
+template <typename T>
+struct DualHalpernEpi {
+    T *y, *ax;
+    const T *b, *y0, *ax0;
+    const State *st;
+    int off;
+    T sigma, lam, rho;
+    __device__ __forceinline__ bool begin() {
+        if (st->status != PDHG_RUNNING) return false;
+        sigma = (T)st->sigma;
+        const double t = (double)(st->t_base + off + 1);
+        lam = (T)(t / (t + 1.0));
+        rho = (T)st->reflect;
+        return true;
+    }
+    __device__ __forceinline__ void operator()(int i, T q) const {
+        const T a = ax[i], yi = y[i];
+        const T yhv = yi + sigma * (b[i] - ((q + q) - a));
+        y[i] = lam * (((T)1 + rho) * yhv - rho * yi) + ((T)1 - lam) * y0[i];
+        ax[i] = lam * (((T)1 + rho) * q - rho * a) + ((T)1 - lam) * ax0[i];
+    }
+};
+
+// Evaluation of T(z) in FP64 arithmetic (storage T): primal part over a row j
+// of A~^T records A~^T y and x^ = max(l, x - tau (c - A~^T y)).
+template <typename T, bool HAS_L>
+struct PrimalEvalEpi {
+    const T *x;
+    const double *c, *l;
+    T *xh;
+    double *aty;
+    const State *st;
+    double tau;
+    __device__ __forceinline__ bool begin() {
+        tau = st->tau;
+        return true;
+    }
+    __device__ __forceinline__ void operator()(int j, double g) const {
+        aty[j] = g;
+        const double v = (double)x[j] - tau * (c[j] - g);
+        const double lj = HAS_L ? l[j] : 0.0;
+        xh[j] = (T)(v < lj ? lj : v);
+    }
+};
+
+// ... dual part over a row i of A~ (q = (A~ x^)_i) records A~ x^ and
+// y^ = y + sigma (b - (2 q - A~x)).
+template <typename T>
+struct DualEvalEpi {
+    const T *y;
+    const double *axc, *b;
+    T *yh;
+    double *axh;
+    const State *st;
+    double sigma;
+    __device__ __forceinline__ bool begin() {
+        sigma = st->sigma;
+        return true;
+    }
+    __device__ __forceinline__ void operator()(int i, double q) const {
+        axh[i] = q;
+        yh[i] = (T)((double)y[i] + sigma * (b[i] - ((q + q) - axc[i])));
+    }
+};
+
 // Adjoint of the dual step, over a row j of A~^T (s = (A~^T gy_{k+1})_j):
 //   gxbar = -sigma s;  g = gx_{k+1} + 2 gxbar;  gv = 1[x_{k+1} > l] g
 //   gx_k = gv - gxbar;  gc -= tau gv
@@ -432,6 +530,51 @@ void launch_dual(const DevCsr &A, const Iter<T> &v, bool avg, const State *st,
         rbT<T>(A, v.x, DualEpi<T, false>{v.y, v.ybar, v.ax, v.bs, st, off}, s);
 }
 
+template <typename T>
+void launch_primal_halpern(const DevCsr &At, const Iter<T> &v, bool has_l,
+                           const State *st, int off, hipStream_t s) {
+    if (has_l)
+        rbT<T>(At, v.y, PrimalHalpernEpi<T, true>{v.x, v.xbar, v.cs, v.ls, v.xl, st, off}, s);
+    else
+        rbT<T>(At, v.y, PrimalHalpernEpi<T, false>{v.x, v.xbar, v.cs, v.ls, v.xl, st, off}, s);
+}
+
+template <typename T>
+void launch_dual_halpern(const DevCsr &A, const Iter<T> &v, const State *st,
+                         int off, hipStream_t s) {
+    rbT<T>(A, (const T *)v.xbar, DualHalpernEpi<T>{v.y, v.ax, v.bs, v.yl, v.ax0, st, off}, s);
+}
+
+template <typename T>
+void launch_eval_T(const DevCsr &A, const DevCsr &At, const Iter<T> &v,
+                   bool has_l, const double *cs, const double *bs,
+                   const double *ls, const State *st, double *aty,
+                   double *axh, const double *axc, hipStream_t s) {
+    if (has_l)
+        rb64(At, SpmvElem<double, T, double>{At.ci, At.v64, v.y},
+             PrimalEvalEpi<T, true>{v.x, cs, ls, v.xbar, aty, st}, s);
+    else
+        rb64(At, SpmvElem<double, T, double>{At.ci, At.v64, v.y},
+             PrimalEvalEpi<T, false>{v.x, cs, ls, v.xbar, aty, st}, s);
+    rb64(A, SpmvElem<double, T, double>{A.ci, A.v64, v.xbar},
+         DualEvalEpi<T>{v.y, axc, bs, v.ybar, axh, st}, s);
+}
+
+#define INST_HALPERN(T)                                                        \
+    template void launch_primal_halpern<T>(const DevCsr &, const Iter<T> &,   \
+                                           bool, const State *, int,          \
+                                           hipStream_t);                      \
+    template void launch_dual_halpern<T>(const DevCsr &, const Iter<T> &,     \
+                                         const State *, int, hipStream_t);    \
+    template void launch_eval_T<T>(const DevCsr &, const DevCsr &,            \
+                                   const Iter<T> &, bool, const double *,     \
+                                   const double *, const double *,            \
+                                   const State *, double *, double *,         \
+                                   const double *, hipStream_t);
+INST_HALPERN(double)
+INST_HALPERN(float)
+#undef INST_HALPERN
+
 template void launch_primal<double>(const DevCsr &, const Iter<double> &, bool,
                                     bool, const State *, int, hipStream_t);
 template void launch_primal<float>(const DevCsr &, const Iter<float> &, bool,
@@ -542,6 +685,10 @@ __global__ __launch_bounds__(kWG) void k_kkt(KktArgs<T> a,
                 const double dy = yv - yli;
                 acc[c][Q_DY2] += dy * dy;
             }
+            if (a.ncand > 1) {
+                const double f = (double)a.y[1][i] - (double)a.y[0][i];
+                acc[1][Q_FY2] += f * f;
+            }
         }
     } else {
         for (int64_t j = (int64_t)(blk - kRedBlocks) * kWG + threadIdx.x;
@@ -563,6 +710,10 @@ __global__ __launch_bounds__(kWG) void k_kkt(KktArgs<T> a,
                 acc[c][Q_LZ] += lj * zs;
                 const double dx = xv - xlj;
                 acc[c][Q_DX2] += dx * dx;
+            }
+            if (a.ncand > 1) {
+                const double f = (double)a.x[1][j] - (double)a.x[0][j];
+                acc[1][Q_FX2] += f * f;
             }
         }
     }
@@ -661,6 +812,84 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
     st->set_last = 0;
     st->snap_n = 0;
 
+    if (st->variant == 1) {
+        // reflected Halpern: candidate 1 is T(z); z itself is not projected,
+        // so T(z) is the reported point; restarts test ||z - T(z)||_omega
+        const double fx2 = tot[1][Q_FX2], fy2 = tot[1][Q_FY2];
+        st->fx2 = fx2;
+        st->fy2 = fy2;
+        const double r_cur = sqrt(om * fx2 + fy2 / om);
+        int restarted = 0;
+        if (!finite || !isfinite(r_cur)) {
+            st->status = PDHG_NUMERICAL;
+        } else {
+            const double mrb = st->stats[1][S_MAXR];
+            int fired = 0;
+            const int first = st->snap_count;
+            while (st->next_level < st->n_levels && mrb <= st->levels[st->next_level]) {
+                const int s = st->snap_count;
+                st->snap_level[s] = st->levels[st->next_level];
+                st->snap_iter[s] = k;
+                st->snap_mr[s] = mrb;
+                st->snap_cand_of[s] = 1;
+                ++st->snap_count;
+                ++st->next_level;
+                ++fired;
+                if (st->literal) break;
+            }
+            if (fired) {
+                st->snap_first = first;
+                st->snap_n = fired;
+                st->snap_cand = 1;
+            }
+            if (mrb <= st->eps_rel) {
+                st->status = PDHG_CONVERGED;
+                st->returned_cand = 1;
+                st->copy_pending = 1;
+                st->copy_avg = 1;
+            } else if (initial) {
+                st->K_last = r_cur;
+            } else {
+                const bool r = (r_cur <= st->beta_suff * st->K_last) ||
+                               (r_cur <= st->beta_nec * st->K_last && r_cur > st->K_prev) ||
+                               ((double)t >= st->beta_art * (double)k);
+                if (r) {
+                    const double *S = st->stats[1];
+                    const double dx = sqrt(S[S_DX2]), dy = sqrt(S[S_DY2]);
+                    if (dx > 1e-10 && dy > 1e-10)
+                        om = exp(st->omega_theta * log(dy / dx) +
+                                 (1.0 - st->omega_theta) * log(om));
+                    st->omega = om;
+                    st->tau = st->eta / om;
+                    st->sigma = st->eta * om;
+                    st->copy_pending = 1;
+                    st->copy_avg = 1;
+                    st->set_last = 1;
+                    st->t_base = 0;
+                    st->K_last = sqrt(om * fx2 + fy2 / om);
+                    st->K_prev = INFINITY;
+                    ++st->restarts;
+                    restarted = 1;
+                } else {
+                    st->K_prev = r_cur;
+                }
+            }
+        }
+        if (elog && st->n_log < st->log_cap) {
+            double *e = elog + 8 * st->n_log;
+            e[0] = (double)k;
+            e[1] = st->stats[0][S_MAXR];
+            e[2] = st->stats[1][S_MAXR];
+            e[3] = r_cur;
+            e[4] = st->K_last;
+            e[5] = (double)restarted;
+            e[6] = 1.0;
+            e[7] = om;
+            ++st->n_log;
+        }
+        return;
+    }
+
     const int best = (ncand > 1 && st->stats[1][S_MAXR] < st->stats[0][S_MAXR]) ? 1 : 0;
     double Kcur = kkt_w(st->stats[0], om);
     double Kavg = ncand > 1 ? kkt_w(st->stats[1], om) : INFINITY;
@@ -757,7 +986,7 @@ __global__ void k_set_status(State *st, int status) {
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_restart_apply(
     const State *__restrict__ st, T *x, T *y, T *ax, T *xbar, T *ybar,
-    const double *ax_avg, T *xl, T *yl, int64_t m, int64_t n) {
+    const double *ax_avg, T *xl, T *yl, T *ax0, int64_t m, int64_t n) {
     if (!st->copy_pending) return;
     const bool avg = st->copy_avg != 0, last = st->set_last != 0;
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -780,6 +1009,7 @@ __global__ __launch_bounds__(kWG) void k_restart_apply(
         if (last) {
             yl[i] = v;
             ybar[i] = (T)0;
+            if (ax0) ax0[i] = avg ? (T)ax_avg[i] : ax[i];
         }
     }
 }
@@ -853,19 +1083,19 @@ void launch_set_status(State *st, int status, hipStream_t s) {
 
 void launch_restart_apply(State *st, bool f32, void *x, void *y, void *ax,
                           void *xbar, void *ybar, const double *ax_avg,
-                          void *xl, void *yl, int64_t m, int64_t n,
+                          void *xl, void *yl, void *ax0, int64_t m, int64_t n,
                           hipStream_t s) {
     const int g = grid_for(n > m ? n : m, kWG, 4096);
     if (f32)
         hipLaunchKernelGGL(k_restart_apply<float>, dim3(g), dim3(kWG), 0, s,
                            st, (float *)x, (float *)y, (float *)ax,
                            (float *)xbar, (float *)ybar, ax_avg,
-                           (float *)xl, (float *)yl, m, n);
+                           (float *)xl, (float *)yl, (float *)ax0, m, n);
     else
         hipLaunchKernelGGL(k_restart_apply<double>, dim3(g), dim3(kWG), 0, s,
                            st, (double *)x, (double *)y, (double *)ax,
                            (double *)xbar, (double *)ybar, ax_avg,
-                           (double *)xl, (double *)yl, m, n);
+                           (double *)xl, (double *)yl, (double *)ax0, m, n);
 }
 
 void launch_snapshot_pack(const State *st, bool f32, const void *x0,

@@ -282,6 +282,7 @@ void free_iter(Iter<T> &v) {
     dfree(v.xl);
     dfree(v.yl);
     dfree(v.ax);
+    dfree(v.ax0);
 }
 
 void invalidate_graph(pdhg_ctx *c) {
@@ -398,6 +399,7 @@ void alloc_iter(Iter<T> &v, int64_t m, int64_t n) {
     v.ybar = dmalloc<T>(m);
     v.yl = dmalloc<T>(m);
     v.ax = dmalloc<T>(m);
+    v.ax0 = dmalloc<T>(m);
 }
 
 template <typename T>
@@ -409,6 +411,7 @@ void zero_iter(pdhg_ctx *c, Iter<T> &v) {
     HIPC(hipMemsetAsync(v.ybar, 0, c->m * sizeof(T), c->stream));
     HIPC(hipMemsetAsync(v.yl, 0, c->m * sizeof(T), c->stream));
     HIPC(hipMemsetAsync(v.ax, 0, c->m * sizeof(T), c->stream));
+    HIPC(hipMemsetAsync(v.ax0, 0, c->m * sizeof(T), c->stream));
 }
 
 double read_scalar(pdhg_ctx *c, const double *dptr) {
@@ -497,6 +500,8 @@ State fresh_state(pdhg_ctx *c, double omega, double nb, double nc) {
     s.beta_nec = c->params.beta_nec;
     s.beta_art = c->params.beta_art;
     s.omega_theta = c->params.omega_theta;
+    s.variant = c->params.variant;
+    s.reflect = c->params.reflect;
     s.status = PDHG_RUNNING;
     s.n_levels = (int)c->levels.size();
     s.literal = c->params.literal_snapshots;
@@ -534,9 +539,24 @@ void current_products(pdhg_ctx *c, bool need_ax) {
 // k = 0 check of the starting point, current iterate only).
 void enqueue_eval(pdhg_ctx *c, int batch, bool initial) {
     const bool h = f32(c);
-    const int ncand = initial ? 1 : 2;
+    const bool halpern = c->params.variant == 1;
+    const int ncand = (initial && !halpern) ? 1 : 2;
     // FP64 products of the candidates
-    if (h) {
+    if (halpern) {
+        // candidate 1 is T(z), computed here in FP64 arithmetic
+        const double *bs = c->act_bs, *cs = c->act_cs;
+        const double *ls = c->act_has_l ? c->act_ls : nullptr;
+        if (h) {
+            spmv_f64_in32(c->A, c->A.v64, c->v32.x, c->ax_cur, c->stream);
+            launch_eval_T<float>(c->A, c->At, c->v32, c->act_has_l, cs, bs, ls,
+                                 c->st, c->aty_cur, c->ax_avg, c->ax_cur, c->stream);
+            spmv_f64_in32(c->At, c->At.v64, c->v32.ybar, c->aty_avg, c->stream);
+        } else {
+            launch_eval_T<double>(c->A, c->At, c->v64, c->act_has_l, cs, bs, ls,
+                                  c->st, c->aty_cur, c->ax_avg, c->v64.ax, c->stream);
+            spmv_f64(c->At, c->At.v64, c->v64.ybar, c->aty_avg, c->stream);
+        }
+    } else if (h) {
         spmv_f64_in32(c->A, c->A.v64, c->v32.x, c->ax_cur, c->stream);
         spmv_f64_in32(c->At, c->At.v64, c->v32.y, c->aty_cur, c->stream);
         if (!initial) {
@@ -570,11 +590,13 @@ void enqueue_eval(pdhg_ctx *c, int batch, bool initial) {
     if (h)
         launch_restart_apply(c->st, true, c->v32.x, c->v32.y, c->v32.ax,
                              c->v32.xbar, c->v32.ybar, c->ax_avg, c->v32.xl,
-                             c->v32.yl, c->m, c->n, c->stream);
+                             c->v32.yl, halpern ? (void *)c->v32.ax0 : nullptr,
+                             c->m, c->n, c->stream);
     else
         launch_restart_apply(c->st, false, c->v64.x, c->v64.y, c->v64.ax,
                              c->v64.xbar, c->v64.ybar, c->ax_avg, c->v64.xl,
-                             c->v64.yl, c->m, c->n, c->stream);
+                             c->v64.yl, halpern ? (void *)c->v64.ax0 : nullptr,
+                             c->m, c->n, c->stream);
     if (h) spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
 }
 
@@ -597,7 +619,12 @@ void enqueue_iterations(pdhg_ctx *c, int first_off, int count) {
             r0.b = pool_event(c);
             HIPC(hipEventRecord(r0.a, c->stream));
         }
-        if (f32(c))
+        const bool halpern = c->params.variant == 1;
+        if (halpern && f32(c))
+            launch_primal_halpern<float>(c->At, c->v32, c->act_has_l, c->st, off, c->stream);
+        else if (halpern)
+            launch_primal_halpern<double>(c->At, c->v64, c->act_has_l, c->st, off, c->stream);
+        else if (f32(c))
             launch_primal<float>(c->At, c->v32, c->act_has_l, true, c->st, off, c->stream);
         else
             launch_primal<double>(c->At, c->v64, c->act_has_l, true, c->st, off, c->stream);
@@ -607,7 +634,11 @@ void enqueue_iterations(pdhg_ctx *c, int first_off, int count) {
             r1.b = pool_event(c);
             HIPC(hipEventRecord(r1.a, c->stream));
         }
-        if (f32(c))
+        if (halpern && f32(c))
+            launch_dual_halpern<float>(c->A, c->v32, c->st, off, c->stream);
+        else if (halpern)
+            launch_dual_halpern<double>(c->A, c->v64, c->st, off, c->stream);
+        else if (f32(c))
             launch_dual<float>(c->A, c->v32, true, c->st, off, c->stream);
         else
             launch_dual<double>(c->A, c->v64, true, c->st, off, c->stream);
@@ -635,6 +666,7 @@ void resolve_profile(pdhg_ctx *c) {
 
 std::vector<const void *> current_graph_key(pdhg_ctx *c) {
     return {(const void *)(intptr_t)c->prec, (const void *)(intptr_t)c->params.eval_every,
+            (const void *)(intptr_t)c->params.variant,
             c->act_bs, c->act_cs, c->act_ls, (const void *)(intptr_t)c->act_has_l,
             cur_x(c), (const void *)(intptr_t)c->n_slots};
 }
@@ -730,12 +762,23 @@ void kkt_pair64(pdhg_ctx *c, const double *xs, const double *ys,
 // Refinement: has the refined point max(0, xo + x^/DP), yo + y^/DD of the
 // current inner iterate reached the round's target on the original LP?
 bool refine_outer_reached(pdhg_ctx *c) {
+    // the Halpern variant reports T(z) (left in xbar / ybar by the
+    // evaluation) unless a restart has just made it the current iterate
+    const bool th = c->params.variant == 1 &&
+                    !(c->st_host->copy_pending && c->st_host->set_last);
+    const float *xi = th ? c->v32.xbar : c->v32.x;
+    const float *yi = th ? c->v32.ybar : c->v32.y;
     HIPC(hipMemcpyAsync(c->xo, c->ref_xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPC(hipMemcpyAsync(c->yo, c->ref_yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    launch_refine_update(c->xo, c->yo, c->v32.x, c->v32.y, c->ref_DP, c->ref_DD, c->m, c->n, c->stream);
+    launch_refine_update(c->xo, c->yo, xi, yi, c->ref_DP, c->ref_DD, c->m, c->n, c->stream);
     pdhg_kkt K;
     kkt_pair64(c, c->xo, c->yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);
-    return K.maxresid <= c->ref_target;
+    const bool ok = K.maxresid <= c->ref_target;
+    if (ok && th) {
+        HIPC(hipMemcpyAsync(c->v32.x, c->v32.xbar, c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v32.y, c->v32.ybar, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    }
+    return ok;
 }
 
 // The iteration loop shared by pdhg_iterate and the refinement's inner
@@ -1106,7 +1149,8 @@ int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
         p->n_levels < 0 || p->n_levels > kMaxLevels ||
         (p->n_levels > 0 && !p->levels) ||
         (p->precision != PDHG_FP64 && p->precision != PDHG_FP32) ||
-        !(p->eps_rel >= 0.0) || p->max_iters < 0)
+        !(p->eps_rel >= 0.0) || p->max_iters < 0 ||
+        (p->variant != 0 && p->variant != 1) || !(p->reflect >= 0.0 && p->reflect <= 1.0))
         return fail(c, PDHG_E_ARG, "invalid parameters");
     for (int i = 1; i < p->n_levels; ++i)
         if (!(p->levels[i] < p->levels[i - 1]))
@@ -1179,6 +1223,7 @@ int pdhg_set_iterate(pdhg_ctx *c, const double *x, const double *y, int mem) {
         HIPC(hipMemcpyAsync(c->v32.xl, c->v32.x, c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         HIPC(hipMemcpyAsync(c->v32.yl, c->v32.y, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
+        HIPC(hipMemcpyAsync(c->v32.ax0, c->v32.ax, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
     } else {
         zero_iter(c, c->v64);
         HIPC(hipMemcpyAsync(c->v64.x, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1186,6 +1231,7 @@ int pdhg_set_iterate(pdhg_ctx *c, const double *x, const double *y, int mem) {
         HIPC(hipMemcpyAsync(c->v64.xl, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPC(hipMemcpyAsync(c->v64.yl, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         spmv_f64(c->A, c->A.v64, c->v64.x, c->v64.ax, c->stream);
+        HIPC(hipMemcpyAsync(c->v64.ax0, c->v64.ax, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     }
     write_state(c, c->st_init);
     *c->st_host = c->st_init;

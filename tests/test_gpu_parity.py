@@ -112,9 +112,10 @@ def _trace_parity(Solver, oracle, lp, K, l=None, **kw):
     return worst
 
 
-def test_iterates_first_100_match_oracle(Solver, oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_iterates_first_100_match_oracle(Solver, oracle, variant):
     lp = lpgen.make("uniform_m500_n1k")
-    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8)
+    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, variant=variant)
     assert worst <= 1e-10, worst
 
 
@@ -125,17 +126,21 @@ def test_iterates_match_with_eval_every_iteration(Solver, oracle):
     assert worst <= 1e-10, worst
 
 
-def test_iterates_match_with_lower_bounds(Solver, oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_iterates_match_with_lower_bounds(Solver, oracle, variant):
     lp = lpgen.planted_uniform(m=800, n=2500, k=6, seed=12)
     l = -np.random.default_rng(12).uniform(0.0, 0.5, lp.n)
-    worst = _trace_parity(Solver, oracle, lp, 100, l=l, eps_rel=1e-8, eval_every=16)
+    worst = _trace_parity(Solver, oracle, lp, 100, l=l, eps_rel=1e-8, eval_every=16,
+                          variant=variant)
     assert worst <= 1e-10, worst
 
 
-def test_iterates_match_multi_tile_ragged(Solver, oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_iterates_match_multi_tile_ragged(Solver, oracle, variant):
     # several tiles per kernel, a ragged last block, short and long rows
     lp = lpgen.planted_powerlaw(m=3000, n=20000, kmax=2500, seed=21)
-    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, eval_every=32)
+    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, eval_every=32,
+                          variant=variant)
     assert worst <= 1e-10, worst
 
 
@@ -147,10 +152,11 @@ def _solve_both(Solver, oracle, lp, levels, eps, **kw):
     return ref, s, st
 
 
-def test_full_solve_kkt_and_snapshots(Solver, oracle):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_full_solve_kkt_and_snapshots(Solver, oracle, variant):
     lp = lpgen.make("uniform_m500_n1k")
     levels = [1e-4, 1e-6]
-    ref, s, st = _solve_both(Solver, oracle, lp, levels, 1e-6)
+    ref, s, st = _solve_both(Solver, oracle, lp, levels, 1e-6, variant=variant)
     inf = s.info()
     assert st == 1 and ref.info["status"] == 1
     assert inf["iters"] == ref.info["iters"]

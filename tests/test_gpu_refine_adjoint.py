@@ -23,8 +23,9 @@ def rel(a, b):
 
 # ------------------------------------------------------------ refinement
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("name", ["uniform", "mcf"])
-def test_fp32_refinement_reaches_1e8(Solver, oracle, name):
+def test_fp32_refinement_reaches_1e8(Solver, oracle, name, variant):
     if name == "uniform":
         lp = lpgen.make("uniform_m500_n1k")
     else:
@@ -32,7 +33,7 @@ def test_fp32_refinement_reaches_1e8(Solver, oracle, name):
     ref = oracle.solve(lp, eps_rel=1e-9)
     assert ref.info["status"] == 1
     with Solver.from_lp(lp) as s:
-        s.configure(eps_rel=1e-8)
+        s.configure(eps_rel=1e-8, variant=variant)
         r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
                             max_inner_iters=50000)
         for row in s.refine_log():
