@@ -36,8 +36,12 @@ def alg_bytes(m: int, n: int, nnz: int, fp: int = 8, has_l: bool = False):
     Each step streams its CSR (values fp bytes + 4-byte column index per
     nonzero, 4-byte row pointers), gathers the other side's vector once, and
     reads / writes its own vectors once.
+    Averaged iteration:
       primal (rows of A^T): x, c, xbar read; x, xbar written (+ l read)
       dual   (rows of A):   y, b, A~x, ybar read; y, A~x, ybar written
+    Reflected Halpern iteration (same counts):
+      primal: x, c, anchor x0 read; x^ = T_x(z) and the new x written
+      dual:   y, b, A~x, anchor y0, A~x0 read; y, A~x written
     """
     primal = (fp + 4) * nnz + 4 * (n + 1) + fp * m + 5 * fp * n + (fp * n if has_l else 0)
     dual = (fp + 4) * nnz + 4 * (m + 1) + fp * n + 7 * fp * m
@@ -56,6 +60,9 @@ def main():
                     help="seconds allowed per time-to-KKT run")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--variant", type=int, default=1,
+                    help="0: averaged iterates with PDLP-style restarts; "
+                         "1: reflected Halpern iteration (default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 256 MiB (reference for "
                          "the profiler's byte counters)")
@@ -85,7 +92,8 @@ def main():
           f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     N = 64
     s = Solver.from_lp(lp, device=0)
-    s.configure(eps_rel=1e-8, eval_every=N, use_graph=0 if args.no_graph else 1)
+    s.configure(eps_rel=1e-8, eval_every=N, use_graph=0 if args.no_graph else 1,
+                variant=args.variant)
     print(f"[bench] configured ({s.info()['t_setup']:.2f}s setup)",
           file=sys.stderr, flush=True)
 
@@ -153,6 +161,7 @@ def main():
         "config": {"workload": args.workload, "m": lp.m, "n": lp.n,
                    "nnz": lp.nnz, "precision": "fp64", "eval_every": N,
                    "ruiz_passes": 10, "eps_rel": 1e-8,
+                   "variant": ["averaged", "halpern"][args.variant],
                    "graphs": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -168,12 +177,12 @@ def main():
     }
 
     if not args.no_ttk:
-        out["time_to_kkt"] = time_to_kkt(Solver, lp, args.ttk_cap)
+        out["time_to_kkt"] = time_to_kkt(Solver, lp, args.ttk_cap, args.variant)
 
     s.close()
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, args.variant)
 
     print(json.dumps(out), flush=True)
 
@@ -187,7 +196,7 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_to_kkt(Solver, lp, cap):
+def time_to_kkt(Solver, lp, cap, variant):
     """Wall time from data resident on the GPU (after load) to FP64 relative
     KKT <= 1e-8: FP64 path vs FP32 bulk + FP64 refinement."""
     import torch
@@ -195,7 +204,7 @@ def time_to_kkt(Solver, lp, cap):
     with Solver.from_lp(lp, device=0) as s:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.configure(eps_rel=1e-8, time_limit_s=cap)
+        s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
         st = s.solve()
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
@@ -208,7 +217,7 @@ def time_to_kkt(Solver, lp, cap):
     with Solver.from_lp(lp, device=0) as s:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.configure(eps_rel=1e-8, time_limit_s=cap)
+        s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
         r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
                             max_inner_iters=5_000_000)
         torch.cuda.synchronize()
@@ -225,12 +234,13 @@ def time_to_kkt(Solver, lp, cap):
     return res
 
 
-def cpu_baseline(lp, iters):
+def cpu_baseline(lp, iters, variant):
     """The FP64 oracle, serial, on the same LP: `iters` iterations (with its
     evaluations at k = 0 and every 64), setup (Ruiz, scaling) excluded."""
     from oracle import oracle
     t0 = time.time()
-    r = oracle.solve(lp, eps_rel=1e-8, max_iters=iters, eta=0.5, omega0=1.0)
+    r = oracle.solve(lp, eps_rel=1e-8, max_iters=iters, eta=0.5, omega0=1.0,
+                     variant=variant)
     wall = time.time() - t0
     ips = r.info["iters"] / r.info["t_iter"]
     print(f"[bench] cpu oracle: {r.info['iters']} iters in {r.info['t_iter']:.2f}s "
