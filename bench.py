@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle")
     ap.add_argument("--ttk-cap", type=float, default=60.0,
                     help="seconds allowed per time-to-KKT run")
+    ap.add_argument("--ttk-runs", type=int, default=3,
+                    help="time-to-KKT runs per path (median reported)")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--variant", type=int, default=1,
@@ -138,12 +140,16 @@ def main():
     print(f"[bench] primal {tp*1e3:.1f}us {gbs_p:.0f}GB/s  dual {td*1e3:.1f}us "
           f"{gbs_d:.0f}GB/s  iteration {iter_gbs:.0f}GB/s", file=sys.stderr, flush=True)
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}.txt")
     if os.path.exists(tfile):
+        tr = {}
         with open(tfile) as f:
-            tr = json.load(f)
+            for line in f:
+                if not line.startswith("#") and ":" in line:
+                    k, v = line.split(":", 1)
+                    tr[k.strip()] = v.strip()
         if tr.get("kernel_source_hash") == _kernel_hash():
-            traffic = tr.get("bytes_per_launch")
+            traffic = int(tr["bytes_per_launch"])
 
     out = {
         "metric": METRIC,
@@ -172,12 +178,14 @@ def main():
                     "dual_step": {"us": round(td * 1e3, 2), "alg_bytes": bd,
                                   "GB_s": round(gbs_d, 1)},
                     "iteration_GB_s": round(iter_gbs, 1),
+                    "steps_only_iters_s": round(1e3 / (tp + td), 1),
                     "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)},
         "restarts_of_run": restarts_of_run,
     }
 
     if not args.no_ttk:
-        out["time_to_kkt"] = time_to_kkt(Solver, lp, args.ttk_cap, args.variant)
+        out["time_to_kkt"] = time_to_kkt(Solver, lp, args.ttk_cap, args.variant,
+                                         args.ttk_runs)
 
     s.close()
 
@@ -196,38 +204,52 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_to_kkt(Solver, lp, cap, variant):
+def time_to_kkt(Solver, lp, cap, variant, runs):
     """Wall time from data resident on the GPU (after load) to FP64 relative
-    KKT <= 1e-8: FP64 path vs FP32 bulk + FP64 refinement."""
+    KKT <= 1e-8: FP64 path vs FP32 bulk + FP64 refinement, `runs` runs each
+    (median reported; the runs are deterministic, so only the time varies)."""
     import torch
-    res = {}
-    with Solver.from_lp(lp, device=0) as s:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
-        st = s.solve()
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        inf = s.info()
-        res["fp64"] = {"seconds": round(t, 3), "status": st, "iters": inf["iters"],
-                       "restarts": inf["restarts"],
-                       "maxresid": inf["kkt"]["maxresid"]}
+
+    def fp64():
+        with Solver.from_lp(lp, device=0) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
+            st = s.solve()
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            inf = s.info()
         print(f"[bench] ttk fp64: {t:.2f}s status {st} iters {inf['iters']} "
-              f"maxresid {inf['kkt']['maxresid']:.2e}", file=sys.stderr, flush=True)
-    with Solver.from_lp(lp, device=0) as s:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
-        r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
-                            max_inner_iters=5_000_000)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        res["fp32_refine"] = {"seconds": round(t, 3), "status": r["status"],
-                              "rounds": r["rounds"], "inner_iters": r["inner_iters"],
-                              "maxresid": r["kkt"]["maxresid"]}
+              f"restarts {inf['restarts']} maxresid {inf['kkt']['maxresid']:.2e}",
+              file=sys.stderr, flush=True)
+        return {"seconds": t, "status": st, "iters": inf["iters"],
+                "restarts": inf["restarts"], "maxresid": inf["kkt"]["maxresid"]}
+
+    def fp32_refine():
+        with Solver.from_lp(lp, device=0) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
+            r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
+                                max_inner_iters=5_000_000)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
         print(f"[bench] ttk fp32+refine: {t:.2f}s status {r['status']} rounds "
               f"{r['rounds']} inner iters {r['inner_iters']} maxresid "
               f"{r['kkt']['maxresid']:.2e}", file=sys.stderr, flush=True)
+        return {"seconds": t, "status": r["status"], "rounds": r["rounds"],
+                "inner_iters": r["inner_iters"], "maxresid": r["kkt"]["maxresid"]}
+
+    res = {}
+    for name, fn in (("fp64", fp64), ("fp32_refine", fp32_refine)):
+        rs = [fn() for _ in range(runs)]
+        ts = sorted(r["seconds"] for r in rs)
+        out = dict(rs[0])
+        out["seconds"] = round(ts[len(ts) // 2], 3)
+        out["runs_s"] = [round(r["seconds"], 3) for r in rs]
+        if any(r["status"] != rs[0]["status"] for r in rs):
+            out["status"] = [r["status"] for r in rs]
+        res[name] = out
     if res["fp64"]["status"] == 1 and res["fp32_refine"]["status"] == 1:
         res["speedup_fp32_refine"] = round(res["fp64"]["seconds"] /
                                            res["fp32_refine"]["seconds"], 3)

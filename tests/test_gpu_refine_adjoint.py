@@ -174,7 +174,7 @@ def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
             fd = np.sum((xp - xm) * (xp + xm - 2 * xt)) / (2 * h)
             scale = max(abs(g[t]), 1e-3 * np.max(np.abs(g)))
             err = abs(fd - g[t]) / scale
-            if err > 1e-4:
+            if err > 1e-6:
                 kw = {"c": "c", "b": "b", "A": "vals"}[group]
                 _, hp = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K, **{kw: p[group]})
                 _, hm = oracle.unrolled_fwd(lp, dr, dc, eta, eta, K, **{kw: q[group]})
