@@ -380,13 +380,41 @@ void pdhg_tape_free(pdhg_tape *tape);
 int pdhg_spmv(pdhg_ctx *ctx, int which, int scaled, int precision,
               const double *in, double *out, int mem);
 
-/* Row-bin tuning: key "split_threshold" (nnz above which a row is split over
- * several workgroups), "split_chunk" (nnz per split part).  Takes effect at
- * the next pdhg_load. */
+/* Row-bin tuning, taking effect at the next pdhg_load:
+ *  "split_threshold": nnz above which a row is split over several
+ *      workgroups; "split_chunk": nnz per split part;
+ *  "panels_a", "panels_at": column panels (1, 2, 4 or 8; 0 = chosen from
+ *      the sizes, the default) of A (the table x the dual step gathers) and
+ *      of A^T (the table y the primal step gathers).  With P > 1 panels an
+ *      SpMV side runs as P column panels, each on the workgroups of 8 / P of
+ *      the 8 XCDs, so that each XCD's L2 holds its panel's part of the
+ *      table; rows are summed over the panels in panel order, so results stay
+ *      deterministic but round differently from P = 1.
+ * Returns PDHG_E_ARG for an unknown key or a value out of range. */
 int pdhg_set_tuning(pdhg_ctx *ctx, const char *key, int64_t value);
 /* Row-block statistics of matrix which (0 = A, 1 = A^T): counts of blocks
  * by kind {multi-row, single-row, split parts} in out[0..2]. */
 int pdhg_bin_stats(pdhg_ctx *ctx, int which, int64_t *out3);
+/* Host-only: the number of column panels (1, 2, 4 or 8) pdhg_load chooses
+ * for an SpMV side of `rows` rows, nnz nonzeros and a gather table of `cols`
+ * FP64 entries, or a negative error code. */
+int pdhg_choose_panels(int64_t rows, int64_t cols, int64_t nnz);
+/* Host-only: the column-panel layout pdhg_load builds for a CSR (rows x cols,
+ * int64 row pointers rp, columns ci sorted within each row) cut at
+ * cut[0] = 0 <= cut[1] <= ... <= cut[P] = cols, P in {1, 2, 4, 8}.
+ * srp (P*rows+1) receives the stacked matrix's row pointers: stacked row
+ * p*rows+i holds row i's entries with column in [cut[p], cut[p+1]); src
+ * (nnz) the position in rp/ci of each stacked entry.  The row blocks for
+ * tile `tile` (no splits) are written to out as (r0, r1, part, nparts), up
+ * to cap blocks, in launch order: block w runs on XCD w % 8, which serves
+ * panel (w % 8) % P; r0 == r1 marks padding.  Returns the number of blocks,
+ * or a negative error code. */
+int pdhg_plan_panels(int64_t rows, int64_t cols, const int64_t *rp,
+                     const int32_t *ci, int P, const int64_t *cut, int tile,
+                     int64_t *srp, int32_t *src, int32_t *out, int64_t cap);
+/* Number of column panels in use for matrix which (0 = A, 1 = A^T) of the
+ * loaded problem, in *panels. */
+int pdhg_panel_count(pdhg_ctx *ctx, int which, int *panels);
 
 /* Enable (1) or disable (0) HIP-event timing of every iteration-kernel
  * launch (batches then run without graphs).  pdhg_kernel_times fills up to

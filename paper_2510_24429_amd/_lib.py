@@ -149,6 +149,9 @@ SIGNATURES = {
     "pdhg_spmv": (i32, [vp, i32, i32, i32, vp, vp, i32]),
     "pdhg_set_tuning": (i32, [vp, C.c_char_p, i64]),
     "pdhg_bin_stats": (i32, [vp, i32, vp]),
+    "pdhg_panel_count": (i32, [vp, i32, vp]),
+    "pdhg_choose_panels": (i32, [i64, i64, i64]),
+    "pdhg_plan_panels": (i32, [i64, i64, vp, vp, i32, vp, i32, vp, vp, vp, i64]),
     "pdhg_profile": (i32, [vp, i32]),
     "pdhg_kernel_times": (i32, [vp, C.POINTER(KernelTime), i32,
                                 C.POINTER(i32), i32]),

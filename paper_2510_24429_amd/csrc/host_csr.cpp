@@ -199,6 +199,39 @@ extern "C" int pdhg_plan_bins(int64_t rows, const int64_t *rp, int tile,
     return (int)k;
 }
 
+extern "C" int pdhg_choose_panels(int64_t rows, int64_t cols, int64_t nnz) {
+    if (rows < 1 || cols < 1 || nnz < 0) return PDHG_E_ARG;
+    return pdhg::choose_panels(rows, cols, nnz);
+}
+
+extern "C" int pdhg_plan_panels(int64_t rows, int64_t cols, const int64_t *rp,
+                                const int32_t *ci, int P, const int64_t *cut,
+                                int tile, int64_t *srp, int32_t *src,
+                                int32_t *out, int64_t cap) {
+    if (rows < 1 || cols < 1 || !rp || !cut || tile < 1 ||
+        !(P == 1 || P == 2 || P == 4 || P == 8) || !srp || !src)
+        return PDHG_E_ARG;
+    if (rp[rows] > 0 && !ci) return PDHG_E_ARG;
+    if (cut[0] != 0 || cut[P] != cols) return PDHG_E_ARG;
+    for (int p = 0; p < P; ++p)
+        if (cut[p + 1] < cut[p]) return PDHG_E_ARG;
+    std::vector<int64_t> vc(cut, cut + P + 1);
+    pdhg::Panels S = pdhg::build_panels(rows, rp, ci, P, vc);
+    std::memcpy(srp, S.rp.data(), S.rp.size() * sizeof(int64_t));
+    if (!S.src.empty())
+        std::memcpy(src, S.src.data(), S.src.size() * sizeof(int32_t));
+    pdhg::HostBins hb = pdhg::build_panel_blocks(rows, S.rp.data(), P, tile,
+                                                 (int64_t)1 << 40, (int64_t)1 << 20);
+    const int64_t k = (int64_t)hb.blocks.size();
+    for (int64_t i = 0; i < k && i < cap && out; ++i) {
+        out[4 * i + 0] = hb.blocks[i].r0;
+        out[4 * i + 1] = hb.blocks[i].r1;
+        out[4 * i + 2] = hb.blocks[i].part;
+        out[4 * i + 3] = hb.blocks[i].nparts;
+    }
+    return (int)k;
+}
+
 namespace pdhg {
 
 // Row-length bins.  Consecutive rows are packed into multi-row blocks of at
@@ -267,9 +300,32 @@ HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
 // sit together, so on skewed matrices most gathers of x hit a small region
 // that stays in cache.  A' keeps each row's entries sorted by the new column
 // index; A'^T is built from A' by one pass with a cursor per column.
+//
+// A dimension split into P > 1 panels (column panels of the gather table of
+// one SpMV side, see choose_panels) is dealt rather than sorted when it is
+// skewed: rank r of the decreasing-length order goes to panel r % P, so every
+// panel holds the same number of entries and the same share of long ones,
+// each panel still in decreasing-length order.  Unskewed dimensions keep
+// their order and are cut into P equal ranges.
+static std::vector<int64_t> deal(std::vector<int32_t> &order, int P) {
+    const int64_t k = (int64_t)order.size();
+    std::vector<int64_t> cut((size_t)P + 1, 0);
+    for (int p = 0; p < P; ++p) cut[p + 1] = cut[p] + (k - p + P - 1) / P;
+    std::vector<int32_t> dealt((size_t)k);
+    for (int64_t r = 0; r < k; ++r) dealt[cut[r % P] + r / P] = order[r];
+    order.swap(dealt);
+    return cut;
+}
+
+static std::vector<int64_t> even_cuts(int64_t k, int P) {
+    std::vector<int64_t> cut((size_t)P + 1);
+    for (int p = 0; p <= P; ++p) cut[p] = k * p / P;
+    return cut;
+}
+
 Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
                   const int32_t *a_ci, const double *a_v,
-                  const int64_t *at_rp) {
+                  const int64_t *at_rp, int panels_a, int panels_at) {
     Relabeled R;
     R.pr.resize((size_t)m);
     R.pc.resize((size_t)n);
@@ -293,6 +349,12 @@ Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
         std::stable_sort(R.pc.begin(), R.pc.end(), [&](int32_t a, int32_t b) {
             return at_rp[a + 1] - at_rp[a] > at_rp[b + 1] - at_rp[b];
         });
+    // panels of A's columns (the table the dual step gathers) and of A^T's
+    // columns, i.e. A's rows (the table the primal step gathers)
+    R.a_cut = (R.sorted_cols && panels_a > 1) ? deal(R.pc, panels_a)
+                                              : even_cuts(n, panels_a);
+    R.at_cut = (R.sorted_rows && panels_at > 1) ? deal(R.pr, panels_at)
+                                                : even_cuts(m, panels_at);
     std::vector<int32_t> ic((size_t)n), ir((size_t)m);
     for (int64_t j = 0; j < n; ++j) ic[R.pc[j]] = (int32_t)j;
     for (int64_t i = 0; i < m; ++i) ir[R.pr[i]] = (int32_t)i;
@@ -345,6 +407,123 @@ Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
         }
     (void)ir;
     return R;
+}
+
+// Column panels and XCD affinity.  A random gather is served at a rate that
+// falls steeply once its table no longer fits the 4 MB L2 of one XCD.
+// Measured on MI355X, random 8-byte gathers per second by table size:
+// <= 2 MB 195e9, 4 MB 180e9, 8 MB 110e9, 16 MB 77e9, 32 MB 63e9,
+// >= 128 MB 54e9.  The same gathers confined per XCD to 1/P of the table run
+// at the rate of the smaller table.  So an SpMV whose table overflows L2 is
+// split into P column panels, each handled only by the workgroups that the
+// hardware places on the XCDs x with x % P == p (workgroups go to the 8 XCDs
+// round-robin by workgroup index).  The price is P stacked rows per row,
+// each with its row pointer, its partial sum written and read once, and its
+// share of the per-row work of the row-block kernel: measured, about 7 ps
+// per stacked row on the whole chip, plus one extra launch that adds the
+// partial sums.  Short rows over a table that fits L2 therefore stay whole.
+static double gather_rate(double bytes) {
+    static const double mb[] = {2, 4, 8, 16, 32, 128};
+    static const double g[] = {195e9, 180e9, 110e9, 77e9, 63e9, 54e9};
+    const double x = bytes / 1048576.0;
+    if (x <= mb[0]) return g[0];
+    for (int i = 1; i < 6; ++i)
+        if (x <= mb[i]) {
+            const double f = std::log(x / mb[i - 1]) / std::log(mb[i] / mb[i - 1]);
+            return g[i - 1] * std::pow(g[i] / g[i - 1], f);
+        }
+    return g[5];
+}
+
+int choose_panels(int64_t rows, int64_t cols, int64_t nnz) {
+    constexpr double kRow = 7e-12;        // seconds per stacked row
+    constexpr double kLaunch = 4e-6;      // the extra launch, seconds
+    const double table = 8.0 * (double)cols;
+    const double whole = (double)nnz / gather_rate(table);
+    double best = 0.85 * whole;           // a split must win clearly
+    int bestP = 1;
+    for (int P = 2; P <= 8; P *= 2) {
+        const double t = (double)nnz / gather_rate(table / P) +
+                         kRow * P * (double)rows + kLaunch;
+        if (t < best) {
+            best = t;
+            bestP = P;
+        }
+    }
+    return bestP;
+}
+
+// The stacked matrix of P column panels: row p * rows + i holds the entries
+// of row i with column in [cut[p], cut[p + 1]) (a contiguous run, since
+// columns are sorted within rows); src maps each entry to its position in
+// the source arrays.
+Panels build_panels(int64_t rows, const int64_t *rp, const int32_t *ci, int P,
+                    const std::vector<int64_t> &cut) {
+    Panels S;
+    const int64_t nnz = rp[rows];
+    S.rp.assign((size_t)P * rows + 1, 0);
+    std::vector<int64_t> start((size_t)P * rows + 1);
+    for (int64_t i = 0; i < rows; ++i) {
+        int64_t q = rp[i];
+        for (int p = 0; p < P; ++p) {
+            start[(size_t)p * rows + i] = q;
+            const int64_t e = rp[i + 1];
+            int64_t q1 = q;
+            while (q1 < e && ci[q1] < cut[p + 1]) ++q1;
+            S.rp[(size_t)p * rows + i + 1] = q1 - q;   // length for now
+            q = q1;
+        }
+    }
+    for (int64_t r = 0; r < (int64_t)P * rows; ++r) S.rp[r + 1] += S.rp[r];
+    S.ci.resize((size_t)nnz);
+    S.src.resize((size_t)nnz);
+    for (int64_t r = 0; r < (int64_t)P * rows; ++r) {
+        const int64_t o = S.rp[r], L = S.rp[r + 1] - o, q0 = start[r];
+        for (int64_t t = 0; t < L; ++t) {
+            S.ci[o + t] = ci[q0 + t];
+            S.src[o + t] = (int32_t)(q0 + t);
+        }
+    }
+    return S;
+}
+
+// Row blocks of the stacked matrix, built per panel and dealt to the XCDs:
+// the blocks of panel p are spread over the XCDs x with x % P == p, and the
+// launch order puts XCD x's i-th block at index 8 i + x (empty blocks, r0 ==
+// r1, pad queues of unequal length).  Split slots are renumbered to be global.
+HostBins build_panel_blocks(int64_t rows, const int64_t *srp, int P, int tile,
+                            int64_t split_threshold, int64_t split_chunk) {
+    constexpr int kXcd = 8;
+    HostBins out;
+    std::vector<std::vector<RowBlock>> q(kXcd);
+    for (int p = 0; p < P; ++p) {
+        HostBins hb = build_row_blocks(rows, srp + (size_t)p * rows, tile,
+                                       split_threshold, split_chunk);
+        const int32_t roff = (int32_t)((int64_t)p * rows);
+        const int slot0 = (int)out.splits.size();
+        for (auto sp : hb.splits) {
+            sp.row += roff;
+            out.splits.push_back(sp);
+        }
+        out.maxparts = std::max(out.maxparts, hb.maxparts);
+        for (int k = 0; k < 3; ++k) out.counts[k] += hb.counts[k];
+        const int per = kXcd / P;     // XCDs serving this panel
+        for (size_t b = 0; b < hb.blocks.size(); ++b) {
+            RowBlock rb = hb.blocks[b];
+            rb.r0 += roff;
+            rb.r1 += roff;
+            if (rb.nparts > 1) rb.slot += slot0;
+            q[p + P * (int)(b % per)].push_back(rb);
+        }
+    }
+    size_t depth = 0;
+    for (auto &v : q) depth = std::max(depth, v.size());
+    out.blocks.reserve(depth * kXcd);
+    for (size_t i = 0; i < depth; ++i)
+        for (int x = 0; x < kXcd; ++x)
+            out.blocks.push_back(i < q[x].size() ? q[x][i]
+                                                 : RowBlock{0, 0, 0, 1, -1, 0, 0, 0});
+    return out;
 }
 
 }  // namespace pdhg

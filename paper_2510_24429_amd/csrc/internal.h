@@ -48,6 +48,19 @@ struct HostBins {
 HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
                           int64_t split_threshold, int64_t split_chunk);
 
+// Column panels of one SpMV side (see host_csr.cpp): the number of panels P
+// (1, 2, 4 or 8) for a matrix of `rows` rows whose gather table has `cols`
+// FP64 entries; the stacked panel matrix; its XCD-dealt row blocks.
+int choose_panels(int64_t rows, int64_t cols, int64_t nnz);
+struct Panels {
+    std::vector<int64_t> rp;      // P * rows + 1
+    std::vector<int32_t> ci, src;
+};
+Panels build_panels(int64_t rows, const int64_t *rp, const int32_t *ci, int P,
+                    const std::vector<int64_t> &cut);
+HostBins build_panel_blocks(int64_t rows, const int64_t *srp, int P, int tile,
+                            int64_t split_threshold, int64_t split_chunk);
+
 // The internal (relabeled) problem: row i' of A' is row pr[i'] of A, column
 // j' of A' is column pc[j'] of A; apos[p'] is the position in A's arrays of
 // A''s nonzero p'; perm[p'] its position in A'^T's arrays.
@@ -58,10 +71,11 @@ struct Relabeled {
     std::vector<int64_t> a_rp, at_rp;
     std::vector<int32_t> a_ci, at_ci;
     std::vector<double> a_v, at_v;
+    std::vector<int64_t> a_cut, at_cut;   // panel boundaries of A' / A'^T columns
 };
 Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
                   const int32_t *a_ci, const double *a_v,
-                  const int64_t *at_rp);
+                  const int64_t *at_rp, int panels_a, int panels_at);
 
 // Matrix resident on the device: CSR with int32 row pointers.
 struct DevCsr {
@@ -82,6 +96,13 @@ struct DevCsr {
     float *part32 = nullptr;
     double *part64_f32blk = nullptr;  // FP64 sums over the FP32 bins
     int64_t counts64[3] = {0, 0, 0};
+    // column panels (P > 1): the stacked panel matrix (P * rows rows, its
+    // values kept equal to v64 / v32 through src), and the partial sums
+    int P = 1;
+    DevCsr *pan = nullptr;
+    int32_t *pan_src = nullptr;
+    double *q64 = nullptr;
+    float *q32 = nullptr;
 };
 
 // Control state of a solve, resident on the device and written only by the

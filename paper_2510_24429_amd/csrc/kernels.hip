@@ -11,6 +11,8 @@
 // are bitwise identical.
 #include <cmath>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace pdhg {
@@ -113,6 +115,16 @@ struct StoreEpi {
     __device__ __forceinline__ void operator()(int r, Acc s) const {
         out[r] = (OutT)s;
     }
+};
+
+// Panel pass: row r of the stacked panel matrix stores its partial sum; the
+// wrapped epilogue's begin() still decides whether the pass runs at all.
+template <class Epi, typename Acc>
+struct PanelEpi {
+    Epi e;
+    Acc *q;
+    __device__ __forceinline__ bool begin() { return e.begin(); }
+    __device__ __forceinline__ void operator()(int r, Acc s) const { q[r] = s; }
 };
 
 // Fused primal step over a row j of A~^T:
@@ -323,6 +335,7 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
     Epi epi = epi_in;
     if (!epi.begin()) return;
     const RowBlock b = blks[blockIdx.x];
+    if (b.r1 == b.r0) return;         // padding of an XCD queue
     const int tid = threadIdx.x;
     if (b.r1 - b.r0 == 1) {
         // one row: the workgroup strides it in aligned groups of four
@@ -439,6 +452,20 @@ __global__ __launch_bounds__(kFixThreads) void k_split_fix(
     epi(r.row, s);
 }
 
+// Rows of a panelled matrix: the P partial sums of row i (stacked rows
+// p * rows + i) added in panel order, then the epilogue.
+template <typename Acc, class Epi>
+__global__ __launch_bounds__(kWG) void k_panel_combine(
+    const Acc *__restrict__ q, int P, int rows, Epi epi_in) {
+    Epi epi = epi_in;
+    if (!epi.begin()) return;
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < rows; i += gridDim.x * kWG) {
+        Acc s = q[i];
+        for (int p = 1; p < P; ++p) s += q[(int64_t)p * rows + i];
+        epi(i, s);
+    }
+}
+
 template <typename Acc, int TILE, class Elem, class Epi>
 void run_rowblock(const RowBlock *blk, int nblk, const SplitRow *split,
                   int nsplit, Acc *part, int maxparts, const int32_t *rp,
@@ -454,24 +481,54 @@ void run_rowblock(const RowBlock *blk, int nblk, const SplitRow *split,
                            maxparts, epi);
 }
 
-// FP64 accumulation always uses the FP64 bins; FP32 accumulation the FP32
-// bins (twice the nonzeros per tile for the same LDS bytes).
-template <class Elem, class Epi>
-void rb64(const DevCsr &M, Elem e, Epi p, hipStream_t s) {
-    run_rowblock<double, kTile64>(M.blk64, M.nblk64, M.split64, M.nsplit64,
-                                  M.part64, M.maxparts64, M.rp, e, p, s);
-}
-template <class Elem, class Epi>
-void rb32(const DevCsr &M, Elem e, Epi p, hipStream_t s) {
-    run_rowblock<float, kTile32>(M.blk32, M.nblk32, M.split32, M.nsplit32,
-                                 M.part32, M.maxparts32, M.rp, e, p, s);
-}
-
 int grid_for(int64_t k, int per = kWG, int cap = 8192) {
     int64_t g = (k + per - 1) / per;
     if (g < 1) g = 1;
     if (g > cap) g = cap;
     return (int)g;
+}
+
+// FP64 accumulation always uses the FP64 bins; FP32 accumulation the FP32
+// bins (twice the nonzeros per tile for the same LDS bytes).
+template <typename Acc, class Elem, class Epi>
+void run_bins(const DevCsr &M, Elem e, Epi p, hipStream_t s) {
+    if constexpr (std::is_same<Acc, double>::value)
+        run_rowblock<double, kTile64>(M.blk64, M.nblk64, M.split64, M.nsplit64,
+                                      M.part64, M.maxparts64, M.rp, e, p, s);
+    else
+        run_rowblock<float, kTile32>(M.blk32, M.nblk32, M.split32, M.nsplit32,
+                                     M.part32, M.maxparts32, M.rp, e, p, s);
+}
+
+// out-row r of M x epilogue, with M's values `vals` (its scaled FP64 or FP32
+// values, or others).  A panelled M runs its scaled values through the panel
+// twin (XCD-dealt panel pass, then the combine with the epilogue); any other
+// value array takes the plain bins.
+template <typename Acc, typename MT, typename VT, class Epi>
+void rb_spmv(const DevCsr &M, const MT *vals, const VT *in, Epi e,
+             hipStream_t s) {
+    const MT *tv = nullptr;
+    if (M.pan) {
+        if constexpr (std::is_same<MT, double>::value) {
+            if (vals == M.v64) tv = M.pan->v64;
+        } else {
+            if (vals == M.v32) tv = M.pan->v32;
+        }
+    }
+    if (!tv) {
+        run_bins<Acc>(M, SpmvElem<MT, VT, Acc>{M.ci, vals, in}, e, s);
+        return;
+    }
+    Acc *q;
+    if constexpr (std::is_same<Acc, double>::value)
+        q = M.q64;
+    else
+        q = M.q32;
+    run_bins<Acc>(*M.pan, SpmvElem<MT, VT, Acc>{M.pan->ci, tv, in},
+                  PanelEpi<Epi, Acc>{e, q}, s);
+    hipLaunchKernelGGL((k_panel_combine<Acc, Epi>),
+                       dim3(grid_for(M.rows, kWG, 4096)), dim3(kWG), 0, s, q,
+                       M.P, (int)M.rows, e);
 }
 
 }  // namespace
@@ -480,19 +537,16 @@ int grid_for(int64_t k, int per = kWG, int cap = 8192) {
 
 void spmv_f64(const DevCsr &M, const double *vals, const double *in,
               double *out, hipStream_t s) {
-    rb64(M, SpmvElem<double, double, double>{M.ci, vals, in},
-         StoreEpi<double, double>{out}, s);
+    rb_spmv<double>(M, vals, in, StoreEpi<double, double>{out}, s);
 }
 
 void spmv_f64_in32(const DevCsr &M, const double *vals, const float *in,
                    double *out, hipStream_t s) {
-    rb64(M, SpmvElem<double, float, double>{M.ci, vals, in},
-         StoreEpi<double, double>{out}, s);
+    rb_spmv<double>(M, vals, in, StoreEpi<double, double>{out}, s);
 }
 
 void spmv_f32(const DevCsr &M, const float *in, float *out, hipStream_t s) {
-    rb32(M, SpmvElem<float, float, float>{M.ci, M.v32, in},
-         StoreEpi<float, float>{out}, s);
+    rb_spmv<float>(M, (const float *)M.v32, in, StoreEpi<float, float>{out}, s);
 }
 
 // ============================================================ PDHG iteration
@@ -500,9 +554,9 @@ void spmv_f32(const DevCsr &M, const float *in, float *out, hipStream_t s) {
 template <typename T, class Epi>
 static void rbT(const DevCsr &M, const T *in, Epi e, hipStream_t s) {
     if constexpr (sizeof(T) == 8)
-        rb64(M, SpmvElem<double, double, double>{M.ci, M.v64, in}, e, s);
+        rb_spmv<double>(M, (const double *)M.v64, in, e, s);
     else
-        rb32(M, SpmvElem<float, float, float>{M.ci, M.v32, in}, e, s);
+        rb_spmv<float>(M, (const float *)M.v32, in, e, s);
 }
 
 template <typename T>
@@ -550,14 +604,15 @@ void launch_eval_T(const DevCsr &A, const DevCsr &At, const Iter<T> &v,
                    bool has_l, const double *cs, const double *bs,
                    const double *ls, const State *st, double *aty,
                    double *axh, const double *axc, hipStream_t s) {
+    const double *atv = At.v64, *av = A.v64;
     if (has_l)
-        rb64(At, SpmvElem<double, T, double>{At.ci, At.v64, v.y},
-             PrimalEvalEpi<T, true>{v.x, cs, ls, v.xbar, aty, st}, s);
+        rb_spmv<double>(At, atv, (const T *)v.y,
+                        PrimalEvalEpi<T, true>{v.x, cs, ls, v.xbar, aty, st}, s);
     else
-        rb64(At, SpmvElem<double, T, double>{At.ci, At.v64, v.y},
-             PrimalEvalEpi<T, false>{v.x, cs, ls, v.xbar, aty, st}, s);
-    rb64(A, SpmvElem<double, T, double>{A.ci, A.v64, v.xbar},
-         DualEvalEpi<T>{v.y, axc, bs, v.ybar, axh, st}, s);
+        rb_spmv<double>(At, atv, (const T *)v.y,
+                        PrimalEvalEpi<T, false>{v.x, cs, ls, v.xbar, aty, st}, s);
+    rb_spmv<double>(A, av, (const T *)v.xbar,
+                    DualEvalEpi<T>{v.y, axc, bs, v.ybar, axh, st}, s);
 }
 
 #define INST_HALPERN(T)                                                        \

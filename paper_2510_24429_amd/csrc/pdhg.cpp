@@ -98,6 +98,7 @@ struct pdhg_ctx {
     bool has_l = false;
     int64_t split_threshold = (int64_t)1 << 20;
     int64_t split_chunk = (int64_t)1 << 16;
+    int panels_a = 0, panels_at = 0;    // column panels per side; 0 = choose
 
     // scaling and scaled data
     double *dr = nullptr, *dc = nullptr;
@@ -259,6 +260,13 @@ std::vector<T> to_host(pdhg_ctx *c, const T *p, int64_t count, int mem) {
 }
 
 void free_csr(DevCsr &M) {
+    if (M.pan) {
+        free_csr(*M.pan);
+        delete M.pan;
+    }
+    dfree(M.pan_src);
+    dfree(M.q64);
+    dfree(M.q32);
     dfree(M.rp);
     dfree(M.ci);
     dfree(M.v_orig);
@@ -340,36 +348,7 @@ void free_problem(pdhg_ctx *c) {
     c->loaded = c->configured = false;
 }
 
-// Upload one CSR (int64 row pointers on the host) and build both bin sets.
-void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
-                int64_t nnz, const std::vector<int64_t> &rp,
-                const std::vector<int32_t> &ci, const std::vector<double> &v) {
-    M.rows = rows;
-    M.cols = cols;
-    M.nnz = nnz;
-    std::vector<int32_t> rp32((size_t)rows + 1);
-    for (int64_t i = 0; i <= rows; ++i) rp32[i] = (int32_t)rp[i];
-    // index and value arrays padded (zeros) to a multiple of 4 plus 4, so the
-    // kernels' aligned 16-byte group loads stay inside the allocation
-    const int64_t pad = ((nnz + 3) & ~(int64_t)3) + 4;
-    M.rp = dmalloc<int32_t>(rows + 1);
-    M.ci = dmalloc<int32_t>(pad);
-    M.v_orig = dmalloc<double>(pad);
-    M.v64 = dmalloc<double>(pad);
-    M.v32 = dmalloc<float>(pad);
-    HIPC(hipMemset(M.ci, 0, pad * sizeof(int32_t)));
-    HIPC(hipMemset(M.v_orig, 0, pad * sizeof(double)));
-    HIPC(hipMemset(M.v64, 0, pad * sizeof(double)));
-    HIPC(hipMemset(M.v32, 0, pad * sizeof(float)));
-    HIPC(hipMemcpy(M.rp, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (nnz > 0) {
-        HIPC(hipMemcpy(M.ci, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
-        HIPC(hipMemcpy(M.v_orig, v.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
-    }
-    // multi-row blocks hold at most TILE - 3 nonzeros: an aligned window of
-    // TILE entries then always covers them
-    HostBins b64 = build_row_blocks(rows, rp.data(), kTile64 - 3, c->split_threshold, c->split_chunk);
-    HostBins b32 = build_row_blocks(rows, rp.data(), kTile32 - 3, c->split_threshold, c->split_chunk);
+void upload_bins(DevCsr &M, const HostBins &b64, const HostBins &b32) {
     M.nblk64 = (int)b64.blocks.size();
     M.nblk32 = (int)b32.blocks.size();
     M.blk64 = dmalloc<RowBlock>(M.nblk64);
@@ -387,6 +366,78 @@ void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
     M.part64 = dmalloc<double>((int64_t)M.nsplit64 * M.maxparts64);
     M.part32 = dmalloc<float>((int64_t)M.nsplit32 * M.maxparts32);
     for (int q = 0; q < 3; ++q) M.counts64[q] = b64.counts[q];
+}
+
+// Index and value arrays padded (zeros) to a multiple of 4 plus 4, so the
+// kernels' aligned 16-byte group loads stay inside the allocation.
+int64_t padded(int64_t nnz) { return ((nnz + 3) & ~(int64_t)3) + 4; }
+
+// The panel twin of M (P > 1): the stacked panel matrix with its own index
+// array and scaled values (filled by apply_scaling), XCD-dealt bins, and the
+// P * rows partial sums.
+void upload_panels(pdhg_ctx *c, DevCsr &M, const std::vector<int64_t> &rp,
+                   const std::vector<int32_t> &ci, int P,
+                   const std::vector<int64_t> &cut) {
+    Panels S = build_panels(M.rows, rp.data(), ci.data(), P, cut);
+    M.P = P;
+    M.pan = new DevCsr();
+    DevCsr &T = *M.pan;
+    T.rows = (int64_t)P * M.rows;
+    T.cols = M.cols;
+    T.nnz = M.nnz;
+    const int64_t pad = padded(M.nnz);
+    std::vector<int32_t> rp32((size_t)T.rows + 1);
+    for (int64_t i = 0; i <= T.rows; ++i) rp32[i] = (int32_t)S.rp[i];
+    T.rp = dmalloc<int32_t>(T.rows + 1);
+    T.ci = dmalloc<int32_t>(pad);
+    T.v64 = dmalloc<double>(pad);
+    T.v32 = dmalloc<float>(pad);
+    HIPC(hipMemset(T.ci, 0, pad * sizeof(int32_t)));
+    HIPC(hipMemset(T.v64, 0, pad * sizeof(double)));
+    HIPC(hipMemset(T.v32, 0, pad * sizeof(float)));
+    HIPC(hipMemcpy(T.rp, rp32.data(), (T.rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    M.pan_src = dmalloc<int32_t>(M.nnz);
+    if (M.nnz) {
+        HIPC(hipMemcpy(T.ci, S.ci.data(), M.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(M.pan_src, S.src.data(), M.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    upload_bins(T, build_panel_blocks(M.rows, S.rp.data(), P, kTile64 - 3, c->split_threshold, c->split_chunk),
+                build_panel_blocks(M.rows, S.rp.data(), P, kTile32 - 3, c->split_threshold, c->split_chunk));
+    M.q64 = dmalloc<double>(T.rows);
+    M.q32 = dmalloc<float>(T.rows);
+}
+
+// Upload one CSR (int64 row pointers on the host) and build both bin sets;
+// with P > 1 also its panel twin.
+void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
+                int64_t nnz, const std::vector<int64_t> &rp,
+                const std::vector<int32_t> &ci, const std::vector<double> &v,
+                int P, const std::vector<int64_t> &cut) {
+    M.rows = rows;
+    M.cols = cols;
+    M.nnz = nnz;
+    std::vector<int32_t> rp32((size_t)rows + 1);
+    for (int64_t i = 0; i <= rows; ++i) rp32[i] = (int32_t)rp[i];
+    const int64_t pad = padded(nnz);
+    M.rp = dmalloc<int32_t>(rows + 1);
+    M.ci = dmalloc<int32_t>(pad);
+    M.v_orig = dmalloc<double>(pad);
+    M.v64 = dmalloc<double>(pad);
+    M.v32 = dmalloc<float>(pad);
+    HIPC(hipMemset(M.ci, 0, pad * sizeof(int32_t)));
+    HIPC(hipMemset(M.v_orig, 0, pad * sizeof(double)));
+    HIPC(hipMemset(M.v64, 0, pad * sizeof(double)));
+    HIPC(hipMemset(M.v32, 0, pad * sizeof(float)));
+    HIPC(hipMemcpy(M.rp, rp32.data(), (rows + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (nnz > 0) {
+        HIPC(hipMemcpy(M.ci, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(M.v_orig, v.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
+    }
+    // multi-row blocks hold at most TILE - 3 nonzeros: an aligned window of
+    // TILE entries then always covers them
+    upload_bins(M, build_row_blocks(rows, rp.data(), kTile64 - 3, c->split_threshold, c->split_chunk),
+                build_row_blocks(rows, rp.data(), kTile32 - 3, c->split_threshold, c->split_chunk));
+    if (P > 1) upload_panels(c, M, rp, ci, P, cut);
 }
 
 template <typename T>
@@ -431,6 +482,11 @@ void apply_scaling(pdhg_ctx *c) {
     launch_scale_values(c->A, c->A.v_orig, c->dr, c->dc, c->A.v64, c->A.v32, c->stream);
     launch_permute(c->At.v64, c->A.v64, c->perm, c->nnz, c->stream);
     launch_to_f32(c->At.v32, c->At.v64, c->nnz, c->stream);
+    for (DevCsr *M : {&c->A, &c->At})
+        if (M->pan) {
+            launch_gather(M->pan->v64, M->v64, M->pan_src, c->nnz, c->stream);
+            launch_to_f32(M->pan->v32, M->pan->v64, c->nnz, c->stream);
+        }
 }
 
 void apply_rhs_scaling(pdhg_ctx *c) {
@@ -1021,6 +1077,15 @@ int pdhg_set_tuning(pdhg_ctx *c, const char *key, int64_t value) {
         c->split_chunk = value;
         return PDHG_OK;
     }
+    const bool pv = value == 0 || value == 1 || value == 2 || value == 4 || value == 8;
+    if (std::strcmp(key, "panels_a") == 0 && pv) {
+        c->panels_a = (int)value;
+        return PDHG_OK;
+    }
+    if (std::strcmp(key, "panels_at") == 0 && pv) {
+        c->panels_at = (int)value;
+        return PDHG_OK;
+    }
     return fail(c, PDHG_E_ARG, "unknown tuning key or value out of range");
 }
 
@@ -1052,12 +1117,16 @@ int pdhg_load(pdhg_ctx *c, int64_t m, int64_t n, int64_t nnz,
     c->m = m;
     c->n = n;
     c->nnz = nnz;
+    // column panels: the dual step gathers x (n entries) over A's rows, the
+    // primal step y (m entries) over A^T's rows
+    const int pa = c->panels_a ? c->panels_a : choose_panels(m, n, nnz);
+    const int pat = c->panels_at ? c->panels_at : choose_panels(n, m, nnz);
     Relabeled R = relabel(m, n, nnz, h_arp.data(), h_aci.data(), h_av.data(),
-                          h_atrp.data());
+                          h_atrp.data(), pa, pat);
     std::vector<int32_t>().swap(h_aci);
     std::vector<double>().swap(h_av);
-    upload_csr(c, c->A, m, n, nnz, R.a_rp, R.a_ci, R.a_v);
-    upload_csr(c, c->At, n, m, nnz, R.at_rp, R.at_ci, R.at_v);
+    upload_csr(c, c->A, m, n, nnz, R.a_rp, R.a_ci, R.a_v, pa, R.a_cut);
+    upload_csr(c, c->At, n, m, nnz, R.at_rp, R.at_ci, R.at_v, pat, R.at_cut);
     std::vector<int32_t> ridx((size_t)nnz);
     for (int64_t i = 0; i < m; ++i)
         for (int64_t p = R.a_rp[i]; p < R.a_rp[i + 1]; ++p) ridx[p] = (int32_t)i;
@@ -1413,6 +1482,13 @@ int pdhg_bin_stats(pdhg_ctx *c, int which, int64_t *out3) {
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
     const DevCsr &M = which ? c->At : c->A;
     for (int q = 0; q < 3; ++q) out3[q] = M.counts64[q];
+    return PDHG_OK;
+}
+
+int pdhg_panel_count(pdhg_ctx *c, int which, int *panels) {
+    if (!c || !panels || which < 0 || which > 1) return PDHG_E_ARG;
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    *panels = (which ? c->At : c->A).P;
     return PDHG_OK;
 }
 

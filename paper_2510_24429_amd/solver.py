@@ -286,6 +286,11 @@ class Solver:
                 self.ctx)
         return out
 
+    def panel_count(self, which: int) -> int:
+        out = C.c_int(0)
+        L.check(self.lib.pdhg_panel_count(self.ctx, which, C.byref(out)), self.ctx)
+        return out.value
+
     def profile(self, enable: bool = True):
         L.check(self.lib.pdhg_profile(self.ctx, int(enable)), self.ctx)
 

@@ -194,3 +194,69 @@ def test_row_bins_cover_every_row_once(seed):
     for row in np.nonzero(lens > thr)[0]:
         parts = blk[(blk[:, 0] == row) & (blk[:, 3] > 1)][:, 2]
         assert list(parts) == list(range(len(parts)))
+
+
+# ---------------------------------------------------------------- panels
+
+def _plan_panels(rp, ci, cols, P, cut, tile=1021):
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    cut = np.ascontiguousarray(cut, dtype=np.int64)
+    rows = len(rp) - 1
+    srp = np.zeros(P * rows + 1, dtype=np.int64)
+    src = np.zeros(max(len(ci), 1), dtype=np.int32)
+    cap = 8 * (P * rows + 8) + 1000
+    out = np.zeros(4 * cap, dtype=np.int32)
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    k = L.lib().pdhg_plan_panels(rows, cols, vp(rp), vp(ci), P, vp(cut), tile,
+                                 vp(srp), vp(src), vp(out), cap)
+    assert k > 0, k
+    return srp, src[:len(ci)], out[:4 * k].reshape(k, 4)
+
+
+@pytest.mark.parametrize("P", [1, 2, 4, 8])
+def test_column_panels_partition_every_row(P):
+    rng = np.random.default_rng(P)
+    lp = lpgen.planted_powerlaw(m=3000, n=9000, kmax=700, seed=P)
+    rows, cols = lp.m, lp.n
+    cut = np.array([cols * p // P for p in range(P + 1)], dtype=np.int64)
+    if P > 2:                       # uneven cuts too
+        cut[1] = cut[1] // 3
+    srp, src, blk = _plan_panels(lp.a_rp, lp.a_ci, cols, P, cut)
+    # stacked row p*rows+i = row i's entries with column in panel p, in order
+    assert srp[0] == 0 and srp[-1] == lp.nnz and np.all(np.diff(srp) >= 0)
+    assert np.array_equal(np.sort(src), np.arange(lp.nnz))
+    for i in rng.integers(0, rows, 200):
+        cols_i = lp.a_ci[lp.a_rp[i]:lp.a_rp[i + 1]]
+        for p in range(P):
+            s0, s1 = srp[p * rows + i], srp[p * rows + i + 1]
+            want = cols_i[(cols_i >= cut[p]) & (cols_i < cut[p + 1])]
+            assert np.array_equal(lp.a_ci[src[s0:s1]], want)
+    # blocks: every stacked row exactly once, a block never leaves its panel,
+    # and the block at launch index w serves panel (w % 8) % P
+    covered = np.zeros(P * rows, dtype=np.int64)
+    for w, (r0, r1, part, nparts) in enumerate(blk):
+        if r0 == r1:
+            continue
+        p = r0 // rows
+        assert (r1 - 1) // rows == p and (w % 8) % P == p
+        assert nparts == 1
+        covered[r0:r1] += 1
+        if r1 - r0 > 1:
+            assert srp[r1] - srp[r0] <= 1021
+    assert np.all(covered == 1)
+    # XCD queues hold whole rows of the 8-wide launch grid
+    assert len(blk) % 8 == 0
+
+
+def test_panel_choice_follows_table_size():
+    # gather tables that fit one XCD's L2 stay whole; an 8 MB table over
+    # long rows is split; short rows over a huge table pay too much in
+    # partial sums for a small table split
+    assert L.lib().pdhg_choose_panels(200_000, 200_000, 9_400_000) == 1
+    assert L.lib().pdhg_choose_panels(200_000, 1_000_000, 9_400_000) > 1
+    assert L.lib().pdhg_choose_panels(1_350_000, 4_950_000, 14_550_000) == 8
+    # ~3 entries per row: splitting the 10.8 MB table costs more than it saves
+    assert L.lib().pdhg_choose_panels(4_950_000, 1_350_000, 14_550_000) == 1
+    assert L.lib().pdhg_choose_panels(100, 100, 0) == 1
+    assert L.lib().pdhg_choose_panels(0, 10, 10) < 0

@@ -57,11 +57,18 @@ def _integer_lp(seed=0):
     return lpgen.from_coo(m, n, rows, cols, vals, np.ones(m), np.ones(n), name="int")
 
 
+PANELS = {"panels_a": 4, "panels_at": 8}
+
+
+@pytest.mark.parametrize("panels", [False, True])
 @pytest.mark.parametrize("split", [False, True])
-def test_spmv_bins_bitwise_on_integers(Solver, split):
+def test_spmv_bins_bitwise_on_integers(Solver, split, panels):
     lp = _integer_lp()
-    tuning = {"split_threshold": 4096, "split_chunk": 1000} if split else None
+    tuning = {"split_threshold": 4096, "split_chunk": 1000} if split else {}
+    if panels:
+        tuning.update(PANELS)
     s = Solver.from_lp(lp, tuning=tuning)
+    assert (s.panel_count(0), s.panel_count(1)) == ((4, 8) if panels else (1, 1))
     st = s.bin_stats(0)
     assert st[0] > 0 and st[1] > 0
     if split:
@@ -76,6 +83,12 @@ def test_spmv_bins_bitwise_on_integers(Solver, split):
     assert np.array_equal(s.spmv(1, y), aty)
     assert np.array_equal(s.spmv(0, x, precision=1), ax)
     assert np.array_equal(s.spmv(1, y, precision=1), aty)
+    # before configure the scaled matrix is A itself (unit factors); the
+    # scaled values take the panel path when the side is panelled
+    assert np.array_equal(s.spmv(0, x, scaled=True), ax)
+    assert np.array_equal(s.spmv(1, y, scaled=True), aty)
+    assert np.array_equal(s.spmv(0, x, scaled=True, precision=1), ax)
+    assert np.array_equal(s.spmv(1, y, scaled=True, precision=1), aty)
     s.close()
 
 
@@ -100,10 +113,10 @@ def test_power_iteration_matches(Solver, oracle):
     assert abs(inf["omega0"] - ref.info["omega0"]) <= 1e-13 * ref.info["omega0"]
 
 
-def _trace_parity(Solver, oracle, lp, K, l=None, **kw):
+def _trace_parity(Solver, oracle, lp, K, l=None, tuning=None, **kw):
     ref = oracle.solve(lp, l=l, trace_k=K, **kw)
     worst = 0.0
-    with Solver.from_lp(lp, lb=l) as s:
+    with Solver.from_lp(lp, lb=l, tuning=tuning) as s:
         s.configure(**kw)
         for k in range(K):
             s.iterate(1)
@@ -126,37 +139,55 @@ def test_iterates_match_with_eval_every_iteration(Solver, oracle):
     assert worst <= 1e-10, worst
 
 
+@pytest.mark.parametrize("panels", [False, True])
 @pytest.mark.parametrize("variant", [0, 1])
-def test_iterates_match_with_lower_bounds(Solver, oracle, variant):
+def test_iterates_match_with_lower_bounds(Solver, oracle, variant, panels):
     lp = lpgen.planted_uniform(m=800, n=2500, k=6, seed=12)
     l = -np.random.default_rng(12).uniform(0.0, 0.5, lp.n)
     worst = _trace_parity(Solver, oracle, lp, 100, l=l, eps_rel=1e-8, eval_every=16,
-                          variant=variant)
+                          variant=variant, tuning=PANELS if panels else None)
     assert worst <= 1e-10, worst
 
 
+@pytest.mark.parametrize("panels", [False, True])
 @pytest.mark.parametrize("variant", [0, 1])
-def test_iterates_match_multi_tile_ragged(Solver, oracle, variant):
+def test_iterates_match_multi_tile_ragged(Solver, oracle, variant, panels):
     # several tiles per kernel, a ragged last block, short and long rows
     lp = lpgen.planted_powerlaw(m=3000, n=20000, kmax=2500, seed=21)
     worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, eval_every=32,
-                          variant=variant)
+                          variant=variant, tuning=PANELS if panels else None)
     assert worst <= 1e-10, worst
 
 
-def _solve_both(Solver, oracle, lp, levels, eps, **kw):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_panelled_fp32_and_fp64_steps_match_plain(Solver, precision):
+    # the panel path changes only the summation order of each row: iterates
+    # stay within rounding of the unpanelled path in both precisions
+    lp = lpgen.planted_powerlaw(m=3000, n=20000, kmax=2500, seed=22)
+    out = []
+    for tuning in (None, PANELS):
+        with Solver.from_lp(lp, tuning=tuning) as s:
+            s.configure(eps_rel=1e-12, precision=precision, eval_every=1024)
+            s.iterate(200)
+            out.append(s.get_iterate()[:2])
+    tol = 1e-11 if precision == 0 else 1e-4
+    assert rel(out[1][0], out[0][0]) <= tol and rel(out[1][1], out[0][1]) <= tol
+
+
+def _solve_both(Solver, oracle, lp, levels, eps, tuning=None, **kw):
     ref = oracle.solve(lp, levels=levels, eps_rel=eps, keep_snap_vectors=True, **kw)
-    s = Solver.from_lp(lp)
+    s = Solver.from_lp(lp, tuning=tuning)
     s.configure(levels=levels, eps_rel=eps, **kw)
     st = s.solve()
     return ref, s, st
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_full_solve_kkt_and_snapshots(Solver, oracle, variant):
+@pytest.mark.parametrize("variant,panels", [(0, False), (1, False), (1, True)])
+def test_full_solve_kkt_and_snapshots(Solver, oracle, variant, panels):
     lp = lpgen.make("uniform_m500_n1k")
     levels = [1e-4, 1e-6]
-    ref, s, st = _solve_both(Solver, oracle, lp, levels, 1e-6, variant=variant)
+    ref, s, st = _solve_both(Solver, oracle, lp, levels, 1e-6, variant=variant,
+                             tuning=PANELS if panels else None)
     inf = s.info()
     assert st == 1 and ref.info["status"] == 1
     assert inf["iters"] == ref.info["iters"]

@@ -24,15 +24,16 @@ def rel(a, b):
 # ------------------------------------------------------------ refinement
 
 @pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("name", ["uniform", "mcf"])
+@pytest.mark.parametrize("name", ["uniform", "mcf", "mcf_panels"])
 def test_fp32_refinement_reaches_1e8(Solver, oracle, name, variant):
     if name == "uniform":
         lp = lpgen.make("uniform_m500_n1k")
     else:
         lp = lpgen.multicommodity(nodes=1500, arcs=6000, commodities=4, seed=2)
+    tuning = {"panels_a": 8, "panels_at": 2} if name == "mcf_panels" else None
     ref = oracle.solve(lp, eps_rel=1e-9)
     assert ref.info["status"] == 1
-    with Solver.from_lp(lp) as s:
+    with Solver.from_lp(lp, tuning=tuning) as s:
         s.configure(eps_rel=1e-8, variant=variant)
         r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
                             max_inner_iters=50000)
@@ -79,13 +80,15 @@ def _adjoint_setup(oracle, lp, ruiz=10):
     return dr, dc, eta
 
 
-def test_unrolled_matches_oracle_reverse_pass(Solver, oracle):
+@pytest.mark.parametrize("panels", [False, True])
+def test_unrolled_matches_oracle_reverse_pass(Solver, oracle, panels):
     lp = lpgen.planted_uniform(m=300, n=700, k=5, seed=41)
     dr, dc, eta = _adjoint_setup(oracle, lp)
     K = 60
     xt = lpgen.target_vector(lp.n, 41)
     xK_or, L_or, gc_or, gb_or, gA_or = oracle.unrolled(lp, dr, dc, eta, eta, K, xt)
-    with Solver.from_lp(lp) as s:
+    tuning = {"panels_a": 2, "panels_at": 4} if panels else None
+    with Solver.from_lp(lp, tuning=tuning) as s:
         s.configure(ruiz_passes=10, power_iters=5)
         grads = {}
         for ck in (1, 7, K):
