@@ -242,7 +242,9 @@ def time_to_kkt(Solver, lp, cap, variant, runs):
 
     res = {}
     for name, fn in (("fp64", fp64), ("fp32_refine", fp32_refine)):
-        rs = [fn() for _ in range(runs)]
+        rs = [fn()]
+        if rs[0]["seconds"] < 20.0:      # repeat only short runs
+            rs += [fn() for _ in range(runs - 1)]
         ts = sorted(r["seconds"] for r in rs)
         out = dict(rs[0])
         out["seconds"] = round(ts[len(ts) // 2], 3)

@@ -140,7 +140,12 @@ typedef struct {
     int64_t max_inner_iters;    /* per inner solve (200000) */
     double progress;            /* an inner solve also stops once the refined
                                    point's FP64 maxresid <= max(outer_eps,
-                                   progress * maxresid before the round) (1e-3) */
+                                   progress * maxresid before the round) (1e-2) */
+    int32_t inner_precision;    /* PDHG_FP32 (default) or PDHG_FP64 inner solves */
+    int32_t omega_carry;        /* 1: a round starts from the previous round's
+                                   final primal weight times
+                                   (D_D/D_D,prev)/(D_P/D_P,prev); 0: from
+                                   ||c^||/||b^|| of the correction LP (1) */
 } pdhg_refine_params;
 
 typedef struct {

@@ -221,7 +221,7 @@ def solve(lp, levels: Sequence[float] = (), l=None, x0=None, y0=None,
 
 
 def refine(lp, outer_eps: float = 1e-8, max_rounds: int = 8,
-           cap_log2: int = 10, progress: float = 1e-3, **inner_kw):
+           cap_log2: int = 10, progress: float = 1e-2, **inner_kw):
     """FP64 iterative refinement with FP64 inner solves (logic check)."""
     rp, ci, v = _csr(lp)
     kw = dict(eps_rel=1e-4)

@@ -80,7 +80,8 @@ class SnapInfo(C.Structure):
 class RefineParams(C.Structure):
     _fields_ = [("outer_eps", C.c_double), ("inner_eps", C.c_double),
                 ("max_rounds", C.c_int32), ("cap_log2", C.c_int32),
-                ("max_inner_iters", C.c_int64), ("progress", C.c_double)]
+                ("max_inner_iters", C.c_int64), ("progress", C.c_double),
+                ("inner_precision", C.c_int32), ("omega_carry", C.c_int32)]
 
 
 class RefineInfo(C.Structure):

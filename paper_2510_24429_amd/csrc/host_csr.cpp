@@ -54,7 +54,9 @@ extern "C" int pdhg_refine_params_default(pdhg_refine_params *p) {
     p->max_rounds = 8;
     p->cap_log2 = 10;
     p->max_inner_iters = 200000;
-    p->progress = 1e-3;
+    p->progress = 1e-2;
+    p->inner_precision = PDHG_FP32;
+    p->omega_carry = 1;
     return PDHG_OK;
 }
 

@@ -260,16 +260,18 @@ void launch_gather(double *dst, const double *src, const int32_t *idx,
 
 // Refinement (FP64): residual data of the correction LP and its update.
 void launch_refine_rhs(const double *bs, const double *ax, const double *cs,
-                       const double *aty, const double *xs, double DP,
-                       double DD, double *bh, double *ch, double *lh,
-                       int64_t m, int64_t n, hipStream_t s);
+                       const double *aty, const double *xs, const double *ls,
+                       double DP, double DD, double *bh, double *ch,
+                       double *lh, int64_t m, int64_t n, hipStream_t s);
 void launch_refine_delta(const double *bs, const double *ax, const double *cs,
                          const double *aty, const double *xs,
-                         const double *dr, const double *dc, int64_t m,
-                         int64_t n, double *partial, double *out2,
+                         const double *ls, const double *dr, const double *dc,
+                         int64_t m, int64_t n, double *partial, double *out2,
                          hipStream_t s);
-void launch_refine_update(double *xs, double *ys, const float *xh,
-                          const float *yh, double DP, double DD, int64_t m,
+// x <- max(l, x + xh / DP), y <- y + yh / DD (ls may be NULL: l = 0)
+template <typename T>
+void launch_refine_update(double *xs, double *ys, const T *xh, const T *yh,
+                          const double *ls, double DP, double DD, int64_t m,
                           int64_t n, hipStream_t s);
 void launch_norm_unscaled(const double *vs, const double *d, int64_t k,
                           double *partial, double *result, hipStream_t s);

@@ -1406,30 +1406,30 @@ __global__ __launch_bounds__(kWG) void k_permute(double *dst,
 // c^ = DD (c~ - A~^T y~), l^ = -DP x~.
 __global__ __launch_bounds__(kWG) void k_refine_rhs(
     const double *bs, const double *ax, const double *cs, const double *aty,
-    const double *xs, double DP, double DD, double *bh, double *ch,
-    double *lh, int64_t m, int64_t n) {
+    const double *xs, const double *ls, double DP, double DD, double *bh,
+    double *ch, double *lh, int64_t m, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m; i += stride)
         bh[i] = DP * (bs[i] - ax[i]);
     for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < n; j += stride) {
         ch[j] = DD * (cs[j] - aty[j]);
-        lh[j] = -DP * xs[j];
+        lh[j] = DP * ((ls ? ls[j] : 0.0) - xs[j]);
     }
 }
 
-// Per block: max |r_P,i| and max (-x_j)^+ (unscaled) into partial[0][b],
-// max (-d_j)^+ into partial[1][b].
+// Per block: max |r_P,i| and max (l_j - x_j)^+ (unscaled) into
+// partial[0][b], max (-d_j)^+ into partial[1][b].
 __global__ __launch_bounds__(kWG) void k_refine_delta(
     const double *bs, const double *ax, const double *cs, const double *aty,
-    const double *xs, const double *dr, const double *dc, int64_t m,
-    int64_t n, double *partial) {
+    const double *xs, const double *ls, const double *dr, const double *dc,
+    int64_t m, int64_t n, double *partial) {
     __shared__ double s_red[4];
     double dp = 0.0, dd = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m; i += stride)
         dp = fmax(dp, fabs((bs[i] - ax[i]) / dr[i]));
     for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < n; j += stride) {
-        dp = fmax(dp, -(dc[j] * xs[j]));
+        dp = fmax(dp, dc[j] * ((ls ? ls[j] : 0.0) - xs[j]));
         dd = fmax(dd, -((cs[j] - aty[j]) / dc[j]));
     }
     dp = block_max(dp, s_red);
@@ -1440,13 +1440,15 @@ __global__ __launch_bounds__(kWG) void k_refine_delta(
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(kWG) void k_refine_update(
-    double *xs, double *ys, const float *xh, const float *yh, double invP,
-    double invD, int64_t m, int64_t n) {
+    double *xs, double *ys, const T *xh, const T *yh, const double *ls,
+    double invP, double invD, int64_t m, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < n; j += stride) {
         const double v = xs[j] + (double)xh[j] * invP;
-        xs[j] = v < 0.0 ? 0.0 : v;
+        const double lj = ls ? ls[j] : 0.0;
+        xs[j] = v < lj ? lj : v;
     }
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m; i += stride)
         ys[i] = ys[i] + (double)yh[i] * invD;
@@ -1548,33 +1550,42 @@ void launch_gather(double *dst, const double *src, const int32_t *idx,
 }
 
 void launch_refine_rhs(const double *bs, const double *ax, const double *cs,
-                       const double *aty, const double *xs, double DP,
-                       double DD, double *bh, double *ch, double *lh,
-                       int64_t m, int64_t n, hipStream_t s) {
+                       const double *aty, const double *xs, const double *ls,
+                       double DP, double DD, double *bh, double *ch,
+                       double *lh, int64_t m, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_refine_rhs, dim3(grid_for(n > m ? n : m, kWG, 4096)),
-                       dim3(kWG), 0, s, bs, ax, cs, aty, xs, DP, DD, bh, ch,
-                       lh, m, n);
+                       dim3(kWG), 0, s, bs, ax, cs, aty, xs, ls, DP, DD, bh,
+                       ch, lh, m, n);
 }
 
 void launch_refine_delta(const double *bs, const double *ax, const double *cs,
                          const double *aty, const double *xs,
-                         const double *dr, const double *dc, int64_t m,
-                         int64_t n, double *partial, double *out2,
+                         const double *ls, const double *dr, const double *dc,
+                         int64_t m, int64_t n, double *partial, double *out2,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_refine_delta, dim3(kRedBlocks), dim3(kWG), 0, s, bs,
-                       ax, cs, aty, xs, dr, dc, m, n, partial);
+                       ax, cs, aty, xs, ls, dr, dc, m, n, partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, s, partial,
                        kRedBlocks, out2, 1);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, s,
                        partial + kRedBlocks, kRedBlocks, out2 + 1, 1);
 }
 
-void launch_refine_update(double *xs, double *ys, const float *xh,
-                          const float *yh, double DP, double DD, int64_t m,
+template <typename T>
+void launch_refine_update(double *xs, double *ys, const T *xh, const T *yh,
+                          const double *ls, double DP, double DD, int64_t m,
                           int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_update, dim3(grid_for(n > m ? n : m, kWG, 4096)),
-                       dim3(kWG), 0, s, xs, ys, xh, yh, 1.0 / DP, 1.0 / DD, m,
-                       n);
+    hipLaunchKernelGGL(k_refine_update<T>,
+                       dim3(grid_for(n > m ? n : m, kWG, 4096)), dim3(kWG), 0,
+                       s, xs, ys, xh, yh, ls, 1.0 / DP, 1.0 / DD, m, n);
 }
+template void launch_refine_update<float>(double *, double *, const float *,
+                                          const float *, const double *,
+                                          double, double, int64_t, int64_t,
+                                          hipStream_t);
+template void launch_refine_update<double>(double *, double *, const double *,
+                                           const double *, const double *,
+                                           double, double, int64_t, int64_t,
+                                           hipStream_t);
 
 }  // namespace pdhg

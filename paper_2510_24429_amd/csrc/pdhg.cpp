@@ -815,26 +815,33 @@ void kkt_pair64(pdhg_ctx *c, const double *xs, const double *ys,
                 const double *bs, const double *cs, const double *ls,
                 double nb, double nc, pdhg_kkt *out);
 
-// Refinement: has the refined point max(0, xo + x^/DP), yo + y^/DD of the
+// Refinement: has the refined point max(l, xo + x^/DP), yo + y^/DD of the
 // current inner iterate reached the round's target on the original LP?
-bool refine_outer_reached(pdhg_ctx *c) {
+template <typename T>
+bool refine_outer_reached_T(pdhg_ctx *c, Iter<T> &v) {
     // the Halpern variant reports T(z) (left in xbar / ybar by the
     // evaluation) unless a restart has just made it the current iterate
     const bool th = c->params.variant == 1 &&
                     !(c->st_host->copy_pending && c->st_host->set_last);
-    const float *xi = th ? c->v32.xbar : c->v32.x;
-    const float *yi = th ? c->v32.ybar : c->v32.y;
+    const T *xi = th ? v.xbar : v.x;
+    const T *yi = th ? v.ybar : v.y;
+    const double *ls = c->has_l ? c->ls : nullptr;
     HIPC(hipMemcpyAsync(c->xo, c->ref_xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPC(hipMemcpyAsync(c->yo, c->ref_yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    launch_refine_update(c->xo, c->yo, xi, yi, c->ref_DP, c->ref_DD, c->m, c->n, c->stream);
+    launch_refine_update<T>(c->xo, c->yo, xi, yi, ls, c->ref_DP, c->ref_DD, c->m, c->n, c->stream);
     pdhg_kkt K;
-    kkt_pair64(c, c->xo, c->yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);
+    kkt_pair64(c, c->xo, c->yo, c->bs, c->cs, ls, c->nb, c->nc, &K);
     const bool ok = K.maxresid <= c->ref_target;
     if (ok && th) {
-        HIPC(hipMemcpyAsync(c->v32.x, c->v32.xbar, c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-        HIPC(hipMemcpyAsync(c->v32.y, c->v32.ybar, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(v.x, v.xbar, c->n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(v.y, v.ybar, c->m * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
     }
     return ok;
+}
+
+bool refine_outer_reached(pdhg_ctx *c) {
+    return c->prec == PDHG_FP64 ? refine_outer_reached_T(c, c->v64)
+                                : refine_outer_reached_T(c, c->v32);
 }
 
 // The iteration loop shared by pdhg_iterate and the refinement's inner
@@ -1633,8 +1640,11 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
         R = *rp;
     else
         pdhg_refine_params_default(&R);
-    if (R.max_rounds < 0 || R.cap_log2 < 0 || R.cap_log2 > 60)
+    if (R.max_rounds < 0 || R.cap_log2 < 0 || R.cap_log2 > 60 ||
+        (R.inner_precision != PDHG_FP32 && R.inner_precision != PDHG_FP64))
         return fail(c, PDHG_E_ARG, "invalid refinement parameters");
+    const bool in64 = R.inner_precision == PDHG_FP64;
+    const double *ls = c->has_l ? c->ls : nullptr;
     const double t0 = now_s();
     alloc_iter(c->v32, c->m, c->n);
     if (!c->bh) {
@@ -1691,7 +1701,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             c->params.time_limit_s = saved.time_limit_s > 0.0 ? left : 0.0;
             // ax_cur = A~ xo, aty_cur = A~^T yo from kkt_pair64
             if (r >= 1) {
-                launch_refine_delta(c->bs, c->ax_cur, c->cs, c->aty_cur, xo,
+                launch_refine_delta(c->bs, c->ax_cur, c->cs, c->aty_cur, xo, ls,
                                     c->dr, c->dc, c->m, c->n, c->partial,
                                     c->scal, c->stream);
                 double d2[2];
@@ -1710,8 +1720,8 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
                 DP = std::min(sP, capP);
                 DD = std::min(sD, capD);
             }
-            launch_refine_rhs(c->bs, c->ax_cur, c->cs, c->aty_cur, xo, DP, DD,
-                              c->bh, c->ch, c->lh, c->m, c->n, c->stream);
+            launch_refine_rhs(c->bs, c->ax_cur, c->cs, c->aty_cur, xo, ls, DP,
+                              DD, c->bh, c->ch, c->lh, c->m, c->n, c->stream);
             launch_to_f32(c->bh32, c->bh, c->m, c->stream);
             launch_to_f32(c->ch32, c->ch, c->n, c->stream);
             launch_to_f32(c->lh32, c->lh, c->n, c->stream);
@@ -1721,17 +1731,28 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             const double nch = std::sqrt(read_scalar(c, c->scal));
             const double nbs = dev_norm(c, c->bh, c->m), ncs = dev_norm(c, c->ch, c->n);
             double om = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
-            if (r >= 1 && omega_end > 0.0) om = omega_end * (DD / DDprev) / (DP / DPprev);
-            // inner solve of the correction LP with FP32 bulk iterations
-            c->prec = PDHG_FP32;
+            if (R.omega_carry && r >= 1 && omega_end > 0.0)
+                om = omega_end * (DD / DDprev) / (DP / DPprev);
+            // inner solve of the correction LP (FP32 bulk iterations unless
+            // FP64 inner solves were asked for)
             c->act_bs = c->bh;
             c->act_cs = c->ch;
             c->act_ls = c->lh;
             c->act_has_l = true;
-            c->v32.bs = c->bh32;
-            c->v32.cs = c->ch32;
-            c->v32.ls = c->lh32;
-            zero_iter(c, c->v32);
+            if (in64) {
+                c->prec = PDHG_FP64;
+                alloc_iter(c->v64, c->m, c->n);
+                c->v64.bs = c->bh;
+                c->v64.cs = c->ch;
+                c->v64.ls = c->lh;
+                zero_iter(c, c->v64);
+            } else {
+                c->prec = PDHG_FP32;
+                c->v32.bs = c->bh32;
+                c->v32.cs = c->ch32;
+                c->v32.ls = c->lh32;
+                zero_iter(c, c->v32);
+            }
             State s = fresh_state(c, om, nbh, nch);
             write_state(c, s);
             reset_solve(c);
@@ -1750,7 +1771,10 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
                                    (double)c->k_host, (double)c->status,
                                    ik.maxresid, now_s() - t0};
             c->refine_log.insert(c->refine_log.end(), rec, rec + 8);
-            launch_refine_update(xo, yo, c->v32.x, c->v32.y, DP, DD, c->m, c->n, c->stream);
+            if (in64)
+                launch_refine_update<double>(xo, yo, c->v64.x, c->v64.y, ls, DP, DD, c->m, c->n, c->stream);
+            else
+                launch_refine_update<float>(xo, yo, c->v32.x, c->v32.y, ls, DP, DD, c->m, c->n, c->stream);
         }
     } catch (...) {
         c->ref_target = -1.0;

@@ -62,6 +62,30 @@ def test_fp32_refinement_reaches_1e8(Solver, oracle, name, variant):
     assert err <= bound(kk) + bound(ref.kkt), (err, bound(kk), bound(ref.kkt))
 
 
+@pytest.mark.parametrize("inner", [1, 0])
+def test_refinement_with_lower_bounds(Solver, oracle, inner):
+    # x >= l with l < 0: the correction LP's bound is Delta_P (l - x) and the
+    # refined x is clipped at l; FP32 and FP64 inner solves
+    lp = lpgen.planted_uniform(m=800, n=2500, k=6, seed=12)
+    l = -np.random.default_rng(12).uniform(0.0, 0.5, lp.n)
+    ref = oracle.solve(lp, l=l, eps_rel=1e-9)
+    assert ref.info["status"] == 1
+    with Solver.from_lp(lp, lb=l) as s:
+        s.configure(eps_rel=1e-8)
+        r = s.solve_refined(outer_eps=1e-8, inner_precision=inner,
+                            max_inner_iters=50000)
+        for row in s.refine_log():
+            print("refine round %d outer %.3e DP %.3g DD %.3g inner iters %d "
+                  "status %d inner %.3e t %.2fs" % tuple(row), flush=True)
+        assert r["status"] == 1, r
+        x, y, _ = s.get_iterate()
+    kk = oracle.kkt(lp, x, y, l=l)
+    assert kk["maxresid"] <= 1e-8, kk
+    assert abs(kk["maxresid"] - r["kkt"]["maxresid"]) <= 1e-12
+    # x = D_c (x~), x~ >= l / D_c: the unscaled bound holds to rounding
+    assert np.all(x >= l - 4 * np.spacing(np.abs(l)))
+
+
 def test_fp32_bulk_solve_reaches_fp32_accuracy(Solver, oracle):
     lp = lpgen.make("uniform_m500_n1k")
     with Solver.from_lp(lp) as s:
