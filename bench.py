@@ -208,6 +208,7 @@ def time_to_kkt(Solver, lp, cap, variant, runs):
     """Wall time from data resident on the GPU (after load) to FP64 relative
     KKT <= 1e-8: FP64 path vs FP32 bulk + FP64 refinement, `runs` runs each
     (median reported; the runs are deterministic, so only the time varies)."""
+    import numpy as np
     import torch
 
     def fp64():
@@ -223,7 +224,8 @@ def time_to_kkt(Solver, lp, cap, variant, runs):
               f"restarts {inf['restarts']} maxresid {inf['kkt']['maxresid']:.2e}",
               file=sys.stderr, flush=True)
         return {"seconds": t, "status": st, "iters": inf["iters"],
-                "restarts": inf["restarts"], "maxresid": inf["kkt"]["maxresid"]}
+                "restarts": inf["restarts"], "maxresid": inf["kkt"]["maxresid"],
+                "pobj": inf["kkt"]["pobj"]}
 
     def fp32_refine():
         with Solver.from_lp(lp, device=0) as s:
@@ -238,7 +240,8 @@ def time_to_kkt(Solver, lp, cap, variant, runs):
               f"{r['rounds']} inner iters {r['inner_iters']} maxresid "
               f"{r['kkt']['maxresid']:.2e}", file=sys.stderr, flush=True)
         return {"seconds": t, "status": r["status"], "rounds": r["rounds"],
-                "inner_iters": r["inner_iters"], "maxresid": r["kkt"]["maxresid"]}
+                "inner_iters": r["inner_iters"], "maxresid": r["kkt"]["maxresid"],
+                "pobj": r["kkt"]["pobj"]}
 
     res = {}
     for name, fn in (("fp64", fp64), ("fp32_refine", fp32_refine)):
@@ -255,6 +258,15 @@ def time_to_kkt(Solver, lp, cap, variant, runs):
     if res["fp64"]["status"] == 1 and res["fp32_refine"]["status"] == 1:
         res["speedup_fp32_refine"] = round(res["fp64"]["seconds"] /
                                            res["fp32_refine"]["seconds"], 3)
+    # objective error of each result: against the planted optimum c^T x* when
+    # the generator planted one, and between the two paths
+    p64 = res["fp64"]["pobj"]
+    if lp.x_star is not None:
+        pstar = float(np.dot(lp.c, lp.x_star))
+        for k in ("fp64", "fp32_refine"):
+            res[k]["obj_rel_err_vs_planted"] = abs(res[k]["pobj"] - pstar) / (1 + abs(pstar))
+    res["fp32_refine"]["obj_rel_diff_vs_fp64"] = (
+        abs(res["fp32_refine"]["pobj"] - p64) / (1 + abs(p64)))
     return res
 
 

@@ -343,8 +343,11 @@ int pdhg_concurrent_crossover(pdhg_ctx *ctx, pdhg_crossover_fn fn, void *user,
  * starts from the previous round's final primal weight rescaled by the change
  * of Delta_D / Delta_P.  Uses the parameters of the last configure (its
  * precision field is ignored; its time_limit_s bounds the whole
- * refinement).  The refined iterate becomes the context's
- * current iterate. */
+ * refinement).  The configured snapshot levels apply to the refined iterate:
+ * its FP64 maxresid is measured before every round and at the end, and
+ * every level it has reached emits a snapshot of it (iter = inner iterations
+ * so far; candidate 0), with the snapshot callback if one is set.  The
+ * refined iterate becomes the context's current iterate. */
 int pdhg_solve_refined(pdhg_ctx *ctx, const pdhg_refine_params *rp,
                        pdhg_refine_info *info);
 

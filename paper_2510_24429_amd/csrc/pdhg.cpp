@@ -73,6 +73,7 @@ struct SnapMeta {
 struct CbItem {
     int idx;
     hipEvent_t ev;
+    pdhg_snapshot_info info;    // copied at enqueue: the list may grow meanwhile
 };
 
 }  // namespace
@@ -142,6 +143,7 @@ struct pdhg_ctx {
     double t_setup = 0, t_iter = 0, t_start = 0;
     std::atomic<int> cancel_flag{0};
     std::vector<SnapMeta> snaps;
+    bool keep_snaps = false;        // refinement: inner solves keep the list
     std::vector<double> refine_log;   // 8 doubles per refinement round
     // outer-progress test of a refinement inner solve (active when set)
     const double *ref_xo = nullptr, *ref_yo = nullptr;
@@ -571,7 +573,7 @@ void reset_solve(pdhg_ctx *c) {
     c->k_host = 0;
     c->status = PDHG_RUNNING;
     c->t_iter = 0;
-    c->snaps.clear();
+    if (!c->keep_snaps) c->snaps.clear();
     c->cancel_flag.store(0);
 }
 
@@ -761,10 +763,11 @@ void cb_worker(pdhg_ctx *c) {
         }
         (void)hipEventSynchronize(it.ev);
         (void)hipEventDestroy(it.ev);
-        pdhg_snapshot_info info = c->snaps[it.idx].info;
-        if (c->cb) c->cb(c->cb_user, it.idx, &info);
+        if (c->cb) c->cb(c->cb_user, it.idx, &it.info);
     }
 }
+
+void start_snapshot_copies(pdhg_ctx *c, int before);
 
 // New snapshots reported by the last evaluation: record their metadata and,
 // when a callback is registered, start their host copy on the copy stream.
@@ -782,6 +785,12 @@ void collect_snapshots(pdhg_ctx *c) {
         sm.slot = s.snap_first;
         c->snaps.push_back(sm);
     }
+    start_snapshot_copies(c, before);
+}
+
+// Snapshots [before, end) share the slot of the first: copy it to pinned host
+// memory on the copy stream and queue their callbacks behind the copy.
+void start_snapshot_copies(pdhg_ctx *c, int before) {
     if (!c->cb || (int)c->snaps.size() == before) return;
     const int64_t len = 2 * c->n + c->m;
     const int slot = c->snaps[before].slot;
@@ -805,7 +814,7 @@ void collect_snapshots(pdhg_ctx *c) {
                 HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
                 HIPC(hipEventRecord(e, c->copy_stream));
             }
-            c->cb_queue.push_back({i, e});
+            c->cb_queue.push_back({i, e, c->snaps[i].info});
         }
     }
     c->cb_cv.notify_one();
@@ -1667,6 +1676,36 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     pdhg_kkt K;
     std::memset(&K, 0, sizeof K);
     c->refine_log.clear();
+    c->snaps.clear();
+    c->keep_snaps = true;
+    // snapshots of the refined iterate at the configured levels, taken
+    // whenever its FP64 maxresid is measured (before every round and at the
+    // end); levels crossed together share one slot
+    size_t next_level = 0;
+    auto snapshot_refined = [&](const pdhg_kkt &KK) {
+        const int before = (int)c->snaps.size();
+        int first = -1;
+        while (next_level < saved_levels.size() && KK.maxresid <= saved_levels[next_level]) {
+            if (first < 0) {
+                first = (int)next_level;
+                double *base = c->slots + (int64_t)first * (2 * c->n + c->m);
+                launch_unscale_xyz(xo, yo, c->aty_cur, c->cs, c->dr, c->dc, c->pr,
+                                   c->pc, base, base + c->n, base + c->n + c->m,
+                                   c->m, c->n, c->stream);
+            }
+            SnapMeta sm;
+            std::memset(&sm, 0, sizeof sm);
+            sm.info.level = saved_levels[next_level];
+            sm.info.iter = inner_total;
+            sm.info.maxresid = KK.maxresid;
+            sm.info.t_wall = now_s() - t0;
+            sm.slot = first;
+            c->snaps.push_back(sm);
+            ++next_level;
+            if (saved.literal_snapshots) break;
+        }
+        start_snapshot_copies(c, before);
+    };
     try {
         c->levels.clear();
         c->n_slots = 0;
@@ -1679,6 +1718,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
                 // close the previous round's record with the resulting KKT
                 c->refine_log[c->refine_log.size() - 8 + 7] = now_s() - t0;
             }
+            snapshot_refined(K);
             if (K.maxresid <= R.outer_eps) {
                 status = PDHG_CONVERGED;
                 break;
@@ -1778,6 +1818,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
         }
     } catch (...) {
         c->ref_target = -1.0;
+        c->keep_snaps = false;
         c->params = saved;
         c->levels = saved_levels;
         c->n_slots = saved_slots;
@@ -1806,6 +1847,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     write_state(c, s);
     *c->st_host = s;
     reset_solve(c);
+    c->keep_snaps = false;
     c->k_host = inner_total;
     c->status = s.status;
     c->initial_done = true;

@@ -80,8 +80,10 @@ class LP:
 
 
 def _csr_pair(m: int, n: int, rows: np.ndarray, cols: np.ndarray,
-              vals: np.ndarray):
-    """CSR of A and of A^T from one coordinate list (entries distinct)."""
+              vals: np.ndarray, log=None):
+    """CSR of A and of A^T from one coordinate list (entries distinct).
+    log(msg), if given, is called after each stage (large inputs take
+    minutes)."""
     rows = rows.astype(np.int64)
     cols = cols.astype(np.int64)
     key = rows * n + cols
@@ -90,12 +92,16 @@ def _csr_pair(m: int, n: int, rows: np.ndarray, cols: np.ndarray,
     a_v = np.ascontiguousarray(vals[o], dtype=np.float64)
     a_rp = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=m), out=a_rp[1:])
+    if log:
+        log("CSR of A built")
     keyt = cols * m + rows
     ot = np.argsort(keyt, kind="stable")
     at_ci = rows[ot].astype(np.int32)
     at_v = np.ascontiguousarray(vals[ot], dtype=np.float64)
     at_rp = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(cols, minlength=n), out=at_rp[1:])
+    if log:
+        log("CSR of A^T built")
     return a_rp, a_ci, a_v, at_rp, at_ci, at_v
 
 
@@ -248,13 +254,15 @@ def multicommodity(nodes: int = 150_000, arcs: int = 600_000,
 
 def planted_coupled(m: int = 5_000_000, n: int = 20_000_000, k: int = 5,
                     n_coupling: int = 50, coupling_len: int = 200_000,
-                    seed: int = 4, name: str = "coupled") -> LP:
+                    seed: int = 4, name: str = "coupled", log=None) -> LP:
     """k distinct rows per column among the first m-R rows, plus R coupling
     rows (the last R rows) each with L distinct random columns; values
-    N(0,1); planted optimum."""
+    N(0,1); planted optimum.  log(msg), if given, reports each stage."""
     rng = np.random.default_rng(seed)
     counts = np.full(n, k, dtype=np.int64)
     cols, rows = _distinct_rows_per_col(rng, counts, 0, m - n_coupling)
+    if log:
+        log("column entries drawn")
     crow, ccol = [], []
     for r in range(n_coupling):
         cc = rng.choice(n, size=coupling_len, replace=False)
@@ -265,7 +273,9 @@ def planted_coupled(m: int = 5_000_000, n: int = 20_000_000, k: int = 5,
         cols = np.concatenate([cols] + ccol)
     vals = rng.standard_normal(cols.shape[0])
     x, y, z, b, c = _plant(rng, rows, cols, vals, m, n)
-    arrs = _csr_pair(m, n, rows, cols, vals)
+    if log:
+        log("coupling rows drawn, optimum planted")
+    arrs = _csr_pair(m, n, rows, cols, vals, log)
     return LP(m, n, *arrs, b=b, c=c, x_star=x, y_star=y, z_star=z, name=name,
               meta=dict(family="coupled", k=k, R=n_coupling, L=coupling_len,
                         seed=seed))

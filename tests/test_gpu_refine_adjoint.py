@@ -86,6 +86,45 @@ def test_refinement_with_lower_bounds(Solver, oracle, inner):
     assert np.all(x >= l - 4 * np.spacing(np.abs(l)))
 
 
+@pytest.mark.parametrize("literal", [0, 1])
+def test_refinement_snapshots_of_refined_iterate(Solver, oracle, literal):
+    # the configured levels apply to the refined iterate; every snapshot
+    # satisfies its level on the original data, recomputed on the CPU
+    import threading
+    lp = lpgen.make("uniform_m500_n1k")
+    levels = [1e-2, 1e-4, 1e-6, 1e-8]
+    seen, ev = [], threading.Event()
+
+    def cb(idx, info):
+        seen.append((idx, info["level"]))
+        if len(seen) == len(levels):
+            ev.set()
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-8, levels=levels, literal_snapshots=literal)
+        s.set_snapshot_callback(cb)
+        r = s.solve_refined(outer_eps=1e-8)
+        assert r["status"] == 1
+        # one level per measurement when literal, so not all may fire
+        cnt = s.snapshot_count()
+        assert 1 <= cnt <= len(levels)
+        if not literal:
+            assert cnt == len(levels)
+            assert ev.wait(10)
+            assert sorted(seen) == list(enumerate(levels))
+        iters = []
+        for i in range(cnt):
+            info, x, y, z = s.snapshot(i)
+            assert info["level"] == levels[i]
+            kk = oracle.kkt(lp, x, y, want_z=True)
+            assert kk["maxresid"] <= info["level"]
+            assert abs(kk["maxresid"] - info["maxresid"]) <= 1e-12
+            assert np.allclose(z, kk["z"], rtol=1e-12, atol=1e-12)
+            iters.append(info["iter"])
+        assert iters == sorted(iters)
+        assert iters[-1] <= r["inner_iters"]
+
+
 def test_fp32_bulk_solve_reaches_fp32_accuracy(Solver, oracle):
     lp = lpgen.make("uniform_m500_n1k")
     with Solver.from_lp(lp) as s:
