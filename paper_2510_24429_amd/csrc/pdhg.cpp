@@ -794,7 +794,8 @@ void start_snapshot_copies(pdhg_ctx *c, int before) {
     if (!c->cb || (int)c->snaps.size() == before) return;
     const int64_t len = 2 * c->n + c->m;
     const int slot = c->snaps[before].slot;
-    if ((int)c->host_snap.size() < c->n_slots) c->host_snap.resize(c->n_slots, nullptr);
+    // (during refinement n_slots is 0 for the inner solves: size by the slot)
+    if ((int)c->host_snap.size() <= slot) c->host_snap.resize(slot + 1, nullptr);
     if (!c->host_snap[slot])
         HIPC(hipHostMalloc((void **)&c->host_snap[slot], len * sizeof(double), hipHostMallocDefault));
     hipEvent_t ready, done;
