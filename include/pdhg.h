@@ -98,6 +98,13 @@ typedef struct {
     int32_t variant;            /* 0: averaged iterates (PDLP-style restarts);
                                    1: reflected Halpern iteration (cuPDLP+-style) */
     double reflect;             /* Halpern reflection rho in [0, 1] (1) */
+    int32_t omega_rule;         /* primal weight at a restart, from the
+                                   distances dx, dy travelled since the last
+                                   one: 0 smoothing, log w += theta (log(dy/dx)
+                                   - log w); 1 PID on e = log(w dx / dy):
+                                   log w -= kp e + ki sum(e) + kd (e - e_prev) */
+    int32_t pad_;
+    double pid_kp, pid_ki, pid_kd;  /* PID gains (0.99, 0.01, 0) */
 } pdhg_params;
 
 /* Relative KKT errors of an unscaled iterate on the original data:

@@ -43,7 +43,10 @@ class Params(C.Structure):
                 ("reflect", C.c_double),
                 ("max_iters", C.c_int64), ("time_limit_s", C.c_double),
                 ("n_levels", C.c_int32), ("pad_", C.c_int32),
-                ("levels", C.POINTER(C.c_double))]
+                ("levels", C.POINTER(C.c_double)),
+                ("omega_rule", C.c_int32), ("pad2_", C.c_int32),
+                ("pid_kp", C.c_double), ("pid_ki", C.c_double),
+                ("pid_kd", C.c_double)]
 
 
 class KKT(C.Structure):
@@ -104,14 +107,15 @@ DEFAULTS = dict(ruiz_passes=10, power_iters=100, eval_every=64,
                 literal_snapshots=0, variant=0, eps_rel=1e-6, eta=0.0,
                 omega0=0.0, eta_factor=0.9, beta_suff=0.2, beta_nec=0.8,
                 beta_art=0.36, omega_theta=0.5, reflect=1.0, max_iters=10**9,
-                time_limit_s=3600.0)
+                time_limit_s=3600.0, omega_rule=0, pid_kp=0.99, pid_ki=0.01,
+                pid_kd=0.0)
 
 
 def make_params(levels: Sequence[float] = (), **kw) -> tuple:
     d = dict(DEFAULTS)
     d.update(kw)
     lv = np.ascontiguousarray(np.asarray(levels, dtype=np.float64))
-    p = Params(**{k: d[k] for k in DEFAULTS}, pad0_=0, n_levels=len(lv), pad_=0,
+    p = Params(**{k: d[k] for k in DEFAULTS}, pad0_=0, n_levels=len(lv), pad_=0, pad2_=0,
                levels=lv.ctypes.data_as(C.POINTER(C.c_double)))
     return p, lv
 

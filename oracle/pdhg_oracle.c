@@ -61,6 +61,9 @@ typedef struct {
     int32_t n_levels;
     int32_t pad_;
     const double *levels;       /* descending snapshot tolerances */
+    int32_t omega_rule;         /* 0 smoothed (omega_theta), 1 PID */
+    int32_t pad2_;
+    double pid_kp, pid_ki, pid_kd;  /* PID gains (0.99, 0.01, 0) */
 } or_params;
 
 typedef struct {
@@ -408,6 +411,35 @@ static int outer_reached(const or_pattern *A, const double *v,
 }
 
 /*
+ * Primal-weight update at a restart, from the distances dx, dy that x and y
+ * travelled since the previous restart (PDLP's balancing idea: omega should
+ * track ||dy|| / ||dx||).  Rule 0 moves log omega the fraction theta of the
+ * way to log(dy / dx).  Rule 1 (the cuPDLP+ family's controller, read here as
+ * PID control of log omega) takes the error e = log(omega dx / dy) and sets
+ *   log omega <- log omega - (kp e + ki sum(e) + kd (e - e_prev)).
+ * Both leave omega unchanged when either distance is below 1e-10.
+ */
+typedef struct {
+    double integral, e_prev;
+} or_pid;
+
+static double omega_update(const or_params *prm, or_pid *pid, double omega,
+                           double dx, double dy) {
+    if (!(dx > 1e-10 && dy > 1e-10)) return omega;
+    if (prm->omega_rule == 1) {
+        const double e = log(omega * dx / dy);
+        pid->integral += e;
+        const double lw = log(omega) - (prm->pid_kp * e +
+                                        prm->pid_ki * pid->integral +
+                                        prm->pid_kd * (e - pid->e_prev));
+        pid->e_prev = e;
+        return exp(lw);
+    }
+    return exp(prm->omega_theta * log(dy / dx) +
+               (1.0 - prm->omega_theta) * log(omega));
+}
+
+/*
  * Reflected Halpern PDHG with restarts (the variant the cuPDLP+ line of work
  * uses; the paper's solver follows it per Section 4.1 but states no details).
  * With T(z) the PDHG step of the averaged variant applied to z = (x, y),
@@ -484,6 +516,7 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
         omega = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
     const double omega0 = omega, rho = prm->reflect;
     double tau = eta / omega, sigma = eta * omega;
+    or_pid pid = {0.0, 0.0};
     prob_t P = {A, v, vs, b, c, lv, bs, cs, ls, dr, dc, nrm2(b, m), nrm2(c, n),
                 wm2, wn2, wm2, wn2, xu, yu};
     /* eval_cand uses wm/wn (first pair) as scratch too: give it its own */
@@ -546,10 +579,8 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
                                   (r_cur <= prm->beta_nec * r_last && r_cur > r_prev) ||
                                   ((double)t >= prm->beta_art * (double)k);
                     if (r) {
-                        const double dx = sqrt(Sh.dx2), dy = sqrt(Sh.dy2);
-                        if (dx > 1e-10 && dy > 1e-10)
-                            omega = exp(prm->omega_theta * log(dy / dx) +
-                                        (1.0 - prm->omega_theta) * log(omega));
+                        omega = omega_update(prm, &pid, omega, sqrt(Sh.dx2),
+                                             sqrt(Sh.dy2));
                         tau = eta / omega;
                         sigma = eta * omega;
                         memcpy(xs, xh, (size_t)n * sizeof(double));
@@ -687,6 +718,7 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
         omega = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
     double omega0 = omega;
     double tau = eta / omega, sigma = eta * omega;
+    or_pid pid = {0.0, 0.0};
 
     prob_t P = {A, v, vs, b, c, lv, bs, cs, ls, dr, dc, nrm2(b, m), nrm2(c, n),
                 wm, wn, wm2, wn2, xu, yu};
@@ -789,10 +821,8 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
                             (Kc <= prm->beta_nec * K_last && Kc > K_prev) ||
                             ((double)t >= prm->beta_art * (double)k);
                     if (r) {
-                        double dx = sqrt(S->dx2), dy = sqrt(S->dy2);
-                        if (dx > 1e-10 && dy > 1e-10)
-                            omega = exp(prm->omega_theta * log(dy / dx) +
-                                        (1.0 - prm->omega_theta) * log(omega));
+                        omega = omega_update(prm, &pid, omega, sqrt(S->dx2),
+                                             sqrt(S->dy2));
                         tau = eta / omega;
                         sigma = eta * omega;
                         if (cand) {

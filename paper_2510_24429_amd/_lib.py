@@ -37,7 +37,10 @@ class Params(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double),
                 ("omega_theta", C.c_double), ("max_iters", C.c_int64),
                 ("time_limit_s", C.c_double), ("use_graph", C.c_int32),
-                ("variant", C.c_int32), ("reflect", C.c_double)]
+                ("variant", C.c_int32), ("reflect", C.c_double),
+                ("omega_rule", C.c_int32), ("pad_", C.c_int32),
+                ("pid_kp", C.c_double), ("pid_ki", C.c_double),
+                ("pid_kd", C.c_double)]
 
 
 class KKT(C.Structure):

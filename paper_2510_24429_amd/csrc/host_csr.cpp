@@ -43,6 +43,10 @@ extern "C" int pdhg_params_default(pdhg_params *p) {
     p->use_graph = 1;
     p->variant = 0;
     p->reflect = 1.0;
+    p->omega_rule = 0;
+    p->pid_kp = 0.99;
+    p->pid_ki = 0.01;
+    p->pid_kd = 0.0;
     return PDHG_OK;
 }
 

@@ -121,6 +121,9 @@ struct State {
     double nb, nc;                  // ||b||_2, ||c||_2 of the unscaled data
     double eps_rel, beta_suff, beta_nec, beta_art, omega_theta;
     double reflect;                 // Halpern reflection
+    double pid_kp, pid_ki, pid_kd;  // PID gains of the primal weight
+    double pid_int, pid_eprev;      // its integral and last error
+    int omega_rule;                 // 0 smoothed, 1 PID
     double fx2, fy2;                // ||z - T(z)||^2 parts at the last evaluation
     long long k;                    // iterations done
     long long t_base;               // iterations since the last restart

@@ -785,6 +785,23 @@ __device__ double kkt_w(const double *S, double w) {
     return sqrt(w * w * S[S_SP2] + S[S_SD2] / (w * w) + S[S_SG] * S[S_SG]);
 }
 
+// Primal weight at a restart from the distances dx, dy travelled since the
+// previous restart: smoothing toward dy / dx in log space (omega_rule 0), or
+// PID control of log omega on the error e = log(omega dx / dy) (rule 1).
+// Unchanged when either distance is below 1e-10.
+__device__ double omega_update(State *st, double om, double dx, double dy) {
+    if (!(dx > 1e-10 && dy > 1e-10)) return om;
+    if (st->omega_rule == 1) {
+        const double e = log(om * dx / dy);
+        st->pid_int += e;
+        const double lw = log(om) - (st->pid_kp * e + st->pid_ki * st->pid_int +
+                                     st->pid_kd * (e - st->pid_eprev));
+        st->pid_eprev = e;
+        return exp(lw);
+    }
+    return exp(st->omega_theta * log(dy / dx) + (1.0 - st->omega_theta) * log(om));
+}
+
 // The decisions of one evaluation, taken by thread 0 after a fixed-order
 // finish of the partial sums.  Mirrors the CPU reference step by step:
 // statistics of both candidates, Algorithm 1's snapshot test on the better
@@ -910,10 +927,7 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
                                ((double)t >= st->beta_art * (double)k);
                 if (r) {
                     const double *S = st->stats[1];
-                    const double dx = sqrt(S[S_DX2]), dy = sqrt(S[S_DY2]);
-                    if (dx > 1e-10 && dy > 1e-10)
-                        om = exp(st->omega_theta * log(dy / dx) +
-                                 (1.0 - st->omega_theta) * log(om));
+                    om = omega_update(st, om, sqrt(S[S_DX2]), sqrt(S[S_DY2]));
                     st->omega = om;
                     st->tau = st->eta / om;
                     st->sigma = st->eta * om;
@@ -987,10 +1001,7 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
                            (Kc <= st->beta_nec * st->K_last && Kc > st->K_prev) ||
                            ((double)t >= st->beta_art * (double)k);
             if (r) {
-                const double dx = sqrt(S[S_DX2]), dy = sqrt(S[S_DY2]);
-                if (dx > 1e-10 && dy > 1e-10)
-                    om = exp(st->omega_theta * log(dy / dx) +
-                             (1.0 - st->omega_theta) * log(om));
+                om = omega_update(st, om, sqrt(S[S_DX2]), sqrt(S[S_DY2]));
                 st->omega = om;
                 st->tau = st->eta / om;
                 st->sigma = st->eta * om;

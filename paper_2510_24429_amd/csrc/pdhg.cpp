@@ -558,6 +558,12 @@ State fresh_state(pdhg_ctx *c, double omega, double nb, double nc) {
     s.beta_nec = c->params.beta_nec;
     s.beta_art = c->params.beta_art;
     s.omega_theta = c->params.omega_theta;
+    s.omega_rule = c->params.omega_rule;
+    s.pid_kp = c->params.pid_kp;
+    s.pid_ki = c->params.pid_ki;
+    s.pid_kd = c->params.pid_kd;
+    s.pid_int = 0.0;
+    s.pid_eprev = 0.0;
     s.variant = c->params.variant;
     s.reflect = c->params.reflect;
     s.status = PDHG_RUNNING;
@@ -1236,7 +1242,8 @@ int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
         (p->n_levels > 0 && !p->levels) ||
         (p->precision != PDHG_FP64 && p->precision != PDHG_FP32) ||
         !(p->eps_rel >= 0.0) || p->max_iters < 0 ||
-        (p->variant != 0 && p->variant != 1) || !(p->reflect >= 0.0 && p->reflect <= 1.0))
+        (p->variant != 0 && p->variant != 1) || !(p->reflect >= 0.0 && p->reflect <= 1.0) ||
+        (p->omega_rule != 0 && p->omega_rule != 1))
         return fail(c, PDHG_E_ARG, "invalid parameters");
     for (int i = 1; i < p->n_levels; ++i)
         if (!(p->levels[i] < p->levels[i - 1]))

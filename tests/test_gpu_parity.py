@@ -211,6 +211,23 @@ def test_full_solve_kkt_and_snapshots(Solver, oracle, variant, panels):
     s.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_pid_primal_weight_matches_oracle(Solver, oracle, variant):
+    lp = lpgen.multicommodity(nodes=300, arcs=1200, commodities=3, seed=4)
+    kw = dict(variant=variant, omega_rule=1, eval_every=32)
+    ref, s, st = _solve_both(Solver, oracle, lp, [1e-4], 1e-8, **kw)
+    inf = s.info()
+    assert st == 1 and ref.info["status"] == 1
+    assert inf["iters"] == ref.info["iters"]
+    assert inf["restarts"] == ref.info["restarts"]
+    assert abs(np.log(inf["omega"]) - np.log(ref.info["omega"])) <= 1e-9
+    for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
+        assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
+    log = s.eval_log()
+    assert np.array_equal(log[:, 5], ref.eval_log[:, 5])          # restarts
+    s.close()
+
+
 def test_full_solve_alg1_schedule_1e8(Solver, oracle):
     lp = lpgen.make("uniform_m500_n1k")
     levels = oracle.alg1_levels(1e-2, 1e-8)

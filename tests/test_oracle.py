@@ -424,3 +424,34 @@ def test_halpern_returns_projected_point(oracle):
     assert np.all(r.x >= l - 4.5e-16 * np.abs(l))
     for i in range(len(r.snaps)):
         assert np.all(r.snap_x[i] >= l - 4.5e-16 * np.abs(l))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_pid_with_proportional_gain_theta_is_the_smoothed_rule(oracle, variant):
+    # log w - theta log(w dx / dy) = (1 - theta) log w + theta log(dy / dx):
+    # the PID rule with kp = theta and no integral or derivative term is the
+    # smoothed rule, up to the rounding of the two log forms
+    lp = lpgen.planted_powerlaw(m=600, n=3000, kmax=300, seed=9)
+    a = oracle.solve(lp, eps_rel=1e-8, variant=variant, omega_rule=0, omega_theta=0.5)
+    b = oracle.solve(lp, eps_rel=1e-8, variant=variant, omega_rule=1, pid_kp=0.5,
+                     pid_ki=0.0, pid_kd=0.0)
+    assert a.info["status"] == b.info["status"] == 1
+    assert a.info["restarts"] == b.info["restarts"]
+    assert abs(a.info["iters"] - b.info["iters"]) <= 64
+    assert abs(np.log(a.info["omega"]) - np.log(b.info["omega"])) <= 1e-6
+
+
+def test_pid_rule_reaches_the_same_optimum(oracle):
+    lp = lpgen.multicommodity(nodes=300, arcs=1200, commodities=3, seed=4)
+    r0 = oracle.solve(lp, eps_rel=1e-8, variant=1)
+    r1 = oracle.solve(lp, eps_rel=1e-8, variant=1, omega_rule=1)
+    assert r0.info["status"] == r1.info["status"] == 1
+    # each objective is within its weak-duality bound of the optimum p*:
+    # pobj - p* <= (pobj - dobj) + ||r_D|| ||x*||, p* - pobj <= ||y*|| ||r_P||
+    # (each run's own point stands in for x*, y*, with 10% slack)
+    def bound(r, o):
+        k = r.kkt
+        nx = 1.1 * max(np.linalg.norm(r.x), np.linalg.norm(o.x))
+        ny = 1.1 * max(np.linalg.norm(r.y), np.linalg.norm(o.y))
+        return abs(k["pobj"] - k["dobj"]) + k["norm_rd"] * nx + k["norm_rp"] * ny
+    assert abs(r0.kkt["pobj"] - r1.kkt["pobj"]) <= bound(r0, r1) + bound(r1, r0)
