@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("levels", C.POINTER(C.c_double)),
                 ("omega_rule", C.c_int32), ("pad2_", C.c_int32),
                 ("pid_kp", C.c_double), ("pid_ki", C.c_double),
-                ("pid_kd", C.c_double)]
+                ("pid_kd", C.c_double), ("stop_on", C.c_int32),
+                ("polish", C.c_int32), ("polish_frac", C.c_double)]
 
 
 class KKT(C.Structure):
@@ -62,11 +63,12 @@ class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("candidate", C.c_int32),
                 ("iters", C.c_int64), ("restarts", C.c_int32),
                 ("n_snap", C.c_int32), ("n_log", C.c_int32),
-                ("pad_", C.c_int32), ("sigma_hat", C.c_double),
+                ("polish_attempts", C.c_int32), ("sigma_hat", C.c_double),
                 ("eta", C.c_double), ("omega0", C.c_double),
                 ("omega", C.c_double), ("tau", C.c_double),
                 ("sigma", C.c_double), ("t_setup", C.c_double),
-                ("t_iter", C.c_double), ("kkt", KKT)]
+                ("t_iter", C.c_double), ("kkt", KKT),
+                ("polish_iters", C.c_int64)]
 
 
 class Snap(C.Structure):
@@ -108,7 +110,7 @@ DEFAULTS = dict(ruiz_passes=10, power_iters=100, eval_every=64,
                 omega0=0.0, eta_factor=0.9, beta_suff=0.2, beta_nec=0.8,
                 beta_art=0.36, omega_theta=0.5, reflect=1.0, max_iters=10**9,
                 time_limit_s=3600.0, omega_rule=0, pid_kp=0.99, pid_ki=0.01,
-                pid_kd=0.0)
+                pid_kd=0.0, stop_on=0, polish=0, polish_frac=0.125)
 
 
 def make_params(levels: Sequence[float] = (), **kw) -> tuple:

@@ -64,6 +64,10 @@ typedef struct {
     int32_t omega_rule;         /* 0 smoothed (omega_theta), 1 PID */
     int32_t pad2_;
     double pid_kp, pid_ki, pid_kd;  /* PID gains (0.99, 0.01, 0) */
+    int32_t stop_on;            /* stop / candidate measure: 0 maxresid,
+                                   1 rel_p only, 2 rel_d only */
+    int32_t polish;             /* 1: feasibility polishing */
+    double polish_frac;         /* phase budget, fraction of k (0.125) */
 } or_params;
 
 typedef struct {
@@ -72,13 +76,14 @@ typedef struct {
 } or_kkt_t;
 
 typedef struct {
-    int32_t status, candidate;  /* candidate: 0 current, 1 average */
+    int32_t status, candidate;  /* candidate: 0 current, 1 average, 2 polished */
     int64_t iters;
     int32_t restarts, n_snap;
-    int32_t n_log, pad_;
+    int32_t n_log, polish_attempts;
     double sigma_hat, eta, omega0, omega, tau, sigma;
     double t_setup, t_iter;
     or_kkt_t kkt;
+    int64_t polish_iters;       /* iterations spent in polishing phases */
 } or_info;
 
 typedef struct {
@@ -439,6 +444,81 @@ static double omega_update(const or_params *prm, or_pid *pid, double omega,
                (1.0 - prm->omega_theta) * log(omega));
 }
 
+/* The measure a solve stops on and picks its candidate by: maxresid, or
+ * for a feasibility phase only the relative primal or dual residual. */
+static double stop_metric(const or_params *prm, const or_kkt_t *K) {
+    return prm->stop_on == 1 ? K->rel_p : prm->stop_on == 2 ? K->rel_d
+                                                            : K->maxresid;
+}
+
+static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
+             const int32_t *ci, const double *v, const double *b,
+             const double *c, const double *l, const double *x0,
+             const double *y0, const or_params *prm, or_info *info,
+             double *x_out, double *y_out, double *z_out, or_snap *snaps,
+             double *snap_x, double *snap_y, double *snap_z, int32_t trace_k,
+             double *trace_x, double *trace_y, int32_t log_cap,
+             double *eval_log, const outer_t *outer);
+
+/*
+ * Feasibility polishing (the PDLP procedure the paper's closing discussion
+ * describes: PDHG phases with a zero objective inside the solve).  Read
+ * here as: at an evaluation at iteration k whose candidate (x, y) already
+ * has a relative gap <= eps_rel but is not yet converged, and once k has
+ * reached the next polishing point,
+ *   1. primal phase: PDHG (same variant, same step size eta and primal
+ *      weight omega, same scaling) on  min 0 s.t. Ax = b, x >= l  from (x, 0),
+ *      until rel_p <= eps_rel or a budget of max(eval_every,
+ *      ceil(polish_frac k / eval_every) eval_every) iterations;
+ *   2. dual phase: PDHG on  min c^T x s.t. Ax = 0, x >= 0  (the dual
+ *      feasibility problem: its dual asks for c - A^T y >= 0) from (0, y),
+ *      until rel_d <= eps_rel or the same budget;
+ *   3. if both phases succeed and the pair (x_p, y_d) has maxresid <= eps_rel
+ *      on the original LP, the solve stops with it; otherwise the main
+ *      iteration continues untouched and the next polishing point is 2k.
+ * x, y are unscaled; on success xp (n), yd (m) hold the polished pair and K
+ * its KKT.  Returns 1 on success.
+ */
+static int polish_attempt(int64_t m, int64_t n, const int64_t *rp,
+                          const int32_t *ci, const double *v, const double *b,
+                          const double *c, const double *l, const double *x,
+                          const double *y, const or_params *prm, double eta,
+                          double omega, int64_t k, double *xp, double *yd,
+                          or_kkt_t *K, int64_t *iters) {
+    const int64_t E = prm->eval_every;
+    int64_t budget = (int64_t)ceil(prm->polish_frac * (double)k / (double)E) * E;
+    if (budget < E) budget = E;
+    or_params ph = *prm;
+    ph.eta = eta;
+    ph.omega0 = omega;
+    ph.max_iters = budget;
+    ph.n_levels = 0;
+    ph.levels = NULL;
+    ph.polish = 0;
+    ph.literal_snapshots = 0;
+    double *zero_n = dalloc(n), *zero_m = dalloc(m);   /* stay zero */
+    double *sx = dalloc(n), *sy = dalloc(m), *sz = dalloc(n);  /* scratch */
+    or_info ip, id;
+    int ok = 0;
+    ph.stop_on = 1;
+    solve_impl(m, n, rp, ci, v, b, zero_n, l, x, NULL, &ph, &ip, xp, sy, sz,
+               NULL, NULL, NULL, NULL, 0, NULL, NULL, 0, NULL, NULL);
+    *iters += ip.iters;
+    if (ip.status == OR_CONVERGED) {
+        ph.stop_on = 2;
+        solve_impl(m, n, rp, ci, v, zero_m, c, NULL, NULL, y, &ph, &id, sx,
+                   yd, sz, NULL, NULL, NULL, NULL, 0, NULL, NULL, 0, NULL,
+                   NULL);
+        *iters += id.iters;
+        if (id.status == OR_CONVERGED) {
+            or_kkt(m, n, rp, ci, v, b, c, l, xp, yd, NULL, K);
+            ok = K->maxresid <= prm->eps_rel;
+        }
+    }
+    free(zero_n); free(zero_m); free(sx); free(sy); free(sz);
+    return ok;
+}
+
 /*
  * Reflected Halpern PDHG with restarts (the variant the cuPDLP+ line of work
  * uses; the paper's solver follows it per Section 4.1 but states no details).
@@ -497,6 +577,7 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
     double *wm = dalloc(m), *wn = dalloc(n), *wm2 = dalloc(m),
            *wn2 = dalloc(n), *xu = dalloc(n), *yu = dalloc(m);
     double *zero_l = dalloc(n);
+    double *xcu = dalloc(n), *ycu = dalloc(m), *xpb = dalloc(n), *ydb = dalloc(m);
     or_ruiz(m, n, rp, ci, v, prm->ruiz_passes, dr, dc, vs);
     const double *lv = l ? l : zero_l;
     for (int64_t i = 0; i < m; ++i) bs[i] = dr[i] * b[i];
@@ -528,8 +609,8 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
     memcpy(ya, ys, (size_t)m * sizeof(double));
     double t1 = now_s();
     int status = OR_RUNNING, restarts = 0, n_snap = 0, next_level = 0;
-    int returned = 0, n_log = 0;
-    int64_t k = 0, t = 0;
+    int returned = 0, n_log = 0, polish_attempts = 0;
+    int64_t k = 0, t = 0, next_polish = 0, polish_iters = 0;
     double r_last = INFINITY, r_prev = INFINITY;
     cand_t Sc, Sh;
     or_kkt_t final_kkt;
@@ -546,7 +627,7 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
             const double r_cur = sqrt(omega * fx + fy / omega);
             const int bi = 1;
             const cand_t *best = &Sh;
-            int restarted = 0;
+            int restarted = 0, polish_due = 0;
             if (!Sc.finite || !Sh.finite || !isfinite(r_cur)) {
                 status = OR_NUMERICAL;
             } else {
@@ -564,7 +645,7 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
                     ++n_snap; ++next_level;
                     if (prm->literal_snapshots) break;
                 }
-                if (best->kkt.maxresid <= prm->eps_rel) {
+                if (stop_metric(prm, &best->kkt) <= prm->eps_rel) {
                     status = OR_CONVERGED;
                     returned = bi;
                     final_kkt = best->kkt;
@@ -575,6 +656,9 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
                 } else if (k == 0) {
                     r_last = r_cur;
                 } else {
+                    polish_due = prm->polish && best->kkt.rel_gap <= prm->eps_rel &&
+                                 k >= next_polish;
+                    if (polish_due) write_unscaled(&P, xh, yh, xcu, ycu, NULL);
                     const int r = (r_cur <= prm->beta_suff * r_last) ||
                                   (r_cur <= prm->beta_nec * r_last && r_cur > r_prev) ||
                                   ((double)t >= prm->beta_art * (double)k);
@@ -595,6 +679,20 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
                     } else {
                         r_prev = r_cur;
                     }
+                }
+            }
+            if (polish_due) {
+                or_kkt_t pk;
+                ++polish_attempts;
+                if (polish_attempt(m, n, rp, ci, v, b, c, l, xcu, ycu, prm, eta,
+                                   omega, k, xpb, ydb, &pk, &polish_iters)) {
+                    status = OR_CONVERGED;
+                    returned = 2;
+                    final_kkt = pk;
+                    for (int64_t j = 0; j < n; ++j) xs[j] = xpb[j] / dc[j];
+                    for (int64_t i = 0; i < m; ++i) ys[i] = ydb[i] / dr[i];
+                } else {
+                    next_polish = 2 * k;
                 }
             }
             if (eval_log && n_log < log_cap) {
@@ -652,6 +750,8 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
         info->restarts = restarts;
         info->n_snap = n_snap;
         info->n_log = n_log;
+        info->polish_attempts = polish_attempts;
+        info->polish_iters = polish_iters;
         info->sigma_hat = sigma_hat;
         info->eta = eta;
         info->omega0 = omega0;
@@ -666,6 +766,7 @@ static int solve_halpern(int64_t m, int64_t n, const int64_t *rp,
     free(ys); free(xh); free(yh); free(xe); free(xa); free(ya); free(wm);
     free(wn); free(wm2); free(wn2); free(xu); free(yu); free(zero_l);
     free(P.wm); free(P.wn);
+    free(xcu); free(ycu); free(xpb); free(ydb);
     return 0;
 }
 
@@ -697,6 +798,8 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
     double *wm = dalloc(m), *wn = dalloc(n), *wm2 = dalloc(m),
            *wn2 = dalloc(n), *xu = dalloc(n), *yu = dalloc(m);
     double *zero_l = dalloc(n);
+    /* polishing: the candidate (unscaled) and the polished pair */
+    double *xcu = dalloc(n), *ycu = dalloc(m), *xpb = dalloc(n), *ydb = dalloc(m);
 
     or_ruiz(m, n, rp, ci, v, prm->ruiz_passes, dr, dc, vs);
     const double *lv = l ? l : zero_l;
@@ -730,8 +833,8 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
     double t1 = now_s();
 
     int status = OR_RUNNING, restarts = 0, n_snap = 0, next_level = 0;
-    int returned = 0, n_log = 0;
-    int64_t k = 0, t = 0;
+    int returned = 0, n_log = 0, polish_attempts = 0;
+    int64_t k = 0, t = 0, next_polish = 0, polish_iters = 0;
     double K_last, K_prev = INFINITY;
     cand_t Sc, Sa, *best;
     or_kkt_t final_kkt;
@@ -753,7 +856,7 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
         ++n_snap; ++next_level;
         if (prm->literal_snapshots) break;
     }
-    if (status == OR_RUNNING && Sc.kkt.maxresid <= prm->eps_rel)
+    if (status == OR_RUNNING && stop_metric(prm, &Sc.kkt) <= prm->eps_rel)
         status = OR_CONVERGED;
     final_kkt = Sc.kkt;
     if (eval_log && n_log < log_cap) {
@@ -783,8 +886,9 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
         if (k % prm->eval_every == 0) {
             eval_cand(&P, xs, ys, xl, yl, &Sc);
             eval_cand(&P, xbar, ybar, xl, yl, &Sa);
-            int bi = (Sa.kkt.maxresid < Sc.kkt.maxresid) ? 1 : 0;
+            int bi = (stop_metric(prm, &Sa.kkt) < stop_metric(prm, &Sc.kkt)) ? 1 : 0;
             best = bi ? &Sa : &Sc;
+            int polish_due = 0;
             double Kc_cur = kkt_w(&Sc, omega), Kc_avg = kkt_w(&Sa, omega);
             int restarted = 0, cand = (Kc_avg < Kc_cur) ? 1 : 0;
             if (!Sc.finite || !Sa.finite) {
@@ -805,7 +909,7 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
                     ++n_snap; ++next_level;
                     if (prm->literal_snapshots) break;
                 }
-                if (best->kkt.maxresid <= prm->eps_rel) {
+                if (stop_metric(prm, &best->kkt) <= prm->eps_rel) {
                     status = OR_CONVERGED;
                     returned = bi;
                     final_kkt = best->kkt;
@@ -814,6 +918,13 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
                         memcpy(ys, ybar, (size_t)m * sizeof(double));
                     }
                 } else {
+                    /* polishing is decided on the candidate before the
+                       restart test may replace it, and runs after it */
+                    polish_due = prm->polish && best->kkt.rel_gap <= prm->eps_rel &&
+                                 k >= next_polish;
+                    if (polish_due)
+                        write_unscaled(&P, bi ? xbar : xs, bi ? ybar : ys, xcu,
+                                       ycu, NULL);
                     /* adaptive restart on KKT_omega */
                     const cand_t *S = cand ? &Sa : &Sc;
                     double Kc = cand ? Kc_avg : Kc_cur;
@@ -843,6 +954,20 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
                     } else {
                         K_prev = Kc;
                     }
+                }
+            }
+            if (polish_due) {
+                or_kkt_t pk;
+                ++polish_attempts;
+                if (polish_attempt(m, n, rp, ci, v, b, c, l, xcu, ycu, prm, eta,
+                                   omega, k, xpb, ydb, &pk, &polish_iters)) {
+                    status = OR_CONVERGED;
+                    returned = 2;
+                    final_kkt = pk;
+                    for (int64_t j = 0; j < n; ++j) xs[j] = xpb[j] / dc[j];
+                    for (int64_t i = 0; i < m; ++i) ys[i] = ydb[i] / dr[i];
+                } else {
+                    next_polish = 2 * k;
                 }
             }
             if (eval_log && n_log < log_cap) {
@@ -884,6 +1009,8 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
         info->restarts = restarts;
         info->n_snap = n_snap;
         info->n_log = n_log;
+        info->polish_attempts = polish_attempts;
+        info->polish_iters = polish_iters;
         info->sigma_hat = sigma_hat;
         info->eta = eta;
         info->omega0 = omega0;
@@ -898,6 +1025,7 @@ static int solve_impl(int64_t m, int64_t n, const int64_t *rp,
     free(xs); free(ys); free(xn); free(xe); free(xbar); free(ybar);
     free(xl); free(yl); free(wm); free(wn); free(wm2); free(wn2);
     free(xu); free(yu); free(zero_l);
+    free(xcu); free(ycu); free(xpb); free(ydb);
     return 0;
 }
 

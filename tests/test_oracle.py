@@ -455,3 +455,58 @@ def test_pid_rule_reaches_the_same_optimum(oracle):
         ny = 1.1 * max(np.linalg.norm(r.y), np.linalg.norm(o.y))
         return abs(k["pobj"] - k["dobj"]) + k["norm_rd"] * nx + k["norm_rp"] * ny
     assert abs(r0.kkt["pobj"] - r1.kkt["pobj"]) <= bound(r0, r1) + bound(r1, r0)
+
+
+# ---------------------------------------------------------- polishing
+
+def _flat_lp(m, n, k, seed):
+    """c = A^T y* with z* = 0: c^T x = y*^T b on the whole feasible set, so
+    every feasible point is optimal and fixing feasibility cannot cost gap."""
+    base = lpgen.planted_uniform(m=m, n=n, k=k, seed=seed)
+    rows = np.repeat(np.arange(m), np.diff(base.a_rp))
+    cols = base.a_ci.astype(np.int64)
+    rng = np.random.default_rng(seed + 100)
+    x = rng.uniform(0.1, 1.0, n)
+    y = rng.standard_normal(m)
+    b = np.bincount(rows, weights=base.a_v * x[cols], minlength=m)
+    c = np.bincount(cols, weights=base.a_v * y[rows], minlength=n)
+    return lpgen.from_coo(m, n, rows, cols, base.a_v, b, c, name="flat")
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_feasibility_stop_measures(oracle, mode):
+    # stop_on = 1 (2) stops on rel_p (rel_d) alone: the returned point meets
+    # that measure, recomputed, and stops no later than the full test
+    lp = lpgen.make("uniform_m500_n1k")
+    full = oracle.solve(lp, eps_rel=1e-6)
+    r = oracle.solve(lp, eps_rel=1e-6, stop_on=mode)
+    k = oracle.kkt(lp, r.x, r.y)
+    assert r.info["status"] == 1
+    assert (k["rel_p"] if mode == 1 else k["rel_d"]) <= 1e-6
+    assert r.info["iters"] <= full.info["iters"]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_polishing_never_alters_the_main_iteration(oracle, variant):
+    # on an LP where no polishing attempt succeeds, the solve with polishing
+    # is the solve without it: same iterations, restarts, point and KKT
+    lp = lpgen.planted_powerlaw(m=1500, n=6000, kmax=600, seed=3)
+    a = oracle.solve(lp, eps_rel=1e-6, variant=variant)
+    b = oracle.solve(lp, eps_rel=1e-6, variant=variant, polish=1)
+    assert b.info["polish_attempts"] >= 1 and b.info["candidate"] != 2
+    assert a.info["iters"] == b.info["iters"]
+    assert a.info["restarts"] == b.info["restarts"]
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
+    assert a.kkt == b.kkt
+
+
+def test_polishing_succeeds_when_feasibility_is_free(oracle):
+    lp = _flat_lp(300, 1000, 5, 1)
+    a = oracle.solve(lp, eps_rel=1e-8, variant=0)
+    b = oracle.solve(lp, eps_rel=1e-8, variant=0, polish=1)
+    assert b.info["status"] == 1 and b.info["candidate"] == 2
+    assert b.info["iters"] < a.info["iters"]
+    k = oracle.kkt(lp, b.x, b.y)
+    assert k["maxresid"] <= 1e-8
+    assert abs(k["maxresid"] - b.kkt["maxresid"]) <= 1e-12
+    assert np.all(b.x >= 0)
