@@ -105,6 +105,13 @@ typedef struct {
                                    log w -= kp e + ki sum(e) + kd (e - e_prev) */
     int32_t pad_;
     double pid_kp, pid_ki, pid_kd;  /* PID gains (0.99, 0.01, 0) */
+    int32_t stop_on;            /* what the eps_rel stop and the candidate
+                                   choice measure: 0 maxresid (default),
+                                   1 rel_p only, 2 rel_d only (feasibility) */
+    int32_t polish;             /* 1: feasibility polishing (see
+                                   pdhg_iterate) */
+    double polish_frac;         /* polishing phase budget as a fraction of
+                                   the iterations so far (0.125) */
 } pdhg_params;
 
 /* Relative KKT errors of an unscaled iterate on the original data:
@@ -123,12 +130,16 @@ typedef struct {
 } pdhg_kkt;
 
 typedef struct {
-    int32_t status, candidate;  /* pdhg_status; returned candidate */
+    int32_t status, candidate;  /* pdhg_status; returned candidate (0 current,
+                                   1 average or T(z), 2 polished pair) */
     int64_t iters;
     int32_t restarts, n_snap;
     double sigma_hat, eta, omega0, omega, tau, sigma;
     double t_setup, t_iter;     /* seconds in configure / in iterate calls */
     pdhg_kkt kkt;               /* of the iterate get_iterate returns */
+    int32_t polish_attempts;    /* feasibility polishing attempts */
+    int32_t pad_;
+    int64_t polish_iters;       /* iterations spent in polishing phases */
 } pdhg_info;
 
 typedef struct {
@@ -267,7 +278,19 @@ int pdhg_set_iterate(pdhg_ctx *ctx, const double *x, const double *y, int mem);
  * z <- lambda((1 + rho)T(z) - rho z) + (1 - lambda) z_0, lambda = t/(t+1) for
  * the t-th step since the restart point z_0; the evaluations use T(z) as the
  * candidate (z itself is not projected), restarts test ||z - T(z)||_omega and
- * restart at T(z), and a stopped solve reports T(z). */
+ * restart at T(z), and a stopped solve reports T(z).
+ * With polish = 1 (feasibility polishing, the procedure the paper's closing
+ * discussion cites): at an evaluation (k > 0) that does not stop, whose
+ * candidate has rel_gap <= eps_rel, and once k has reached the next
+ * polishing point (initially 0), the candidate is set aside before the
+ * restart test; after it, a primal phase (same variant, step size and primal
+ * weight) solves min 0 s.t. Ax = b, x >= l from (candidate x, 0) until rel_p
+ * <= eps_rel, and a dual phase solves min c^T x s.t. Ax = 0, x >= 0 from
+ * (0, candidate y) until rel_d <= eps_rel, each within max(eval_every,
+ * ceil(polish_frac k / eval_every) eval_every) iterations.  If both succeed
+ * and the pair has maxresid <= eps_rel the solve stops with it (candidate 2);
+ * otherwise the main iteration continues unchanged and the next polishing
+ * point is 2k. */
 int pdhg_iterate(pdhg_ctx *ctx, int64_t max_iters, int *status);
 
 /* Ask a running pdhg_iterate / pdhg_solve_refined to stop at its next

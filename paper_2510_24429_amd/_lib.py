@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("variant", C.c_int32), ("reflect", C.c_double),
                 ("omega_rule", C.c_int32), ("pad_", C.c_int32),
                 ("pid_kp", C.c_double), ("pid_ki", C.c_double),
-                ("pid_kd", C.c_double)]
+                ("pid_kd", C.c_double), ("stop_on", C.c_int32),
+                ("polish", C.c_int32), ("polish_frac", C.c_double)]
 
 
 class KKT(C.Structure):
@@ -63,7 +64,9 @@ class Info(C.Structure):
                 ("eta", C.c_double), ("omega0", C.c_double),
                 ("omega", C.c_double), ("tau", C.c_double),
                 ("sigma", C.c_double), ("t_setup", C.c_double),
-                ("t_iter", C.c_double), ("kkt", KKT)]
+                ("t_iter", C.c_double), ("kkt", KKT),
+                ("polish_attempts", C.c_int32), ("pad_", C.c_int32),
+                ("polish_iters", C.c_int64)]
 
     def asdict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "kkt"}

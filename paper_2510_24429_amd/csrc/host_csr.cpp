@@ -47,6 +47,9 @@ extern "C" int pdhg_params_default(pdhg_params *p) {
     p->pid_kp = 0.99;
     p->pid_ki = 0.01;
     p->pid_kd = 0.0;
+    p->stop_on = 0;
+    p->polish = 0;
+    p->polish_frac = 0.125;
     return PDHG_OK;
 }
 

@@ -124,6 +124,12 @@ struct State {
     double pid_kp, pid_ki, pid_kd;  // PID gains of the primal weight
     double pid_int, pid_eprev;      // its integral and last error
     int omega_rule;                 // 0 smoothed, 1 PID
+    int stop_on;                    // stop measure: 0 maxresid, 1 rel_p, 2 rel_d
+    int polish;                     // feasibility polishing enabled
+    int polish_due;                 // this evaluation asks for an attempt
+    int polish_cand;                // from candidate 0 or 1
+    int pad_polish;
+    long long next_polish;          // earliest iteration of the next attempt
     double fx2, fy2;                // ||z - T(z)||^2 parts at the last evaluation
     long long k;                    // iterations done
     long long t_base;               // iterations since the last restart
@@ -200,6 +206,12 @@ void launch_kkt_reduce(int ncand, const void *x0, const void *y0,
                        double *partial, hipStream_t s);
 void launch_control(State *st, const double *partial, int ncand, int batch,
                     int initial, double *log, hipStream_t s);
+// When the evaluation asked for a polishing attempt: the candidate it chose,
+// unscaled (D_c x, D_r y) in FP64, into xs / ys (before any restart moves it).
+void launch_polish_stash(const State *st, bool f32, const void *x0,
+                         const void *y0, const void *x1, const void *y1,
+                         const double *dr, const double *dc, double *xs,
+                         double *ys, int64_t m, int64_t n, hipStream_t s);
 void launch_advance(State *st, int batch, hipStream_t s);
 void launch_set_status(State *st, int status, hipStream_t s);
 void launch_restart_apply(State *st, bool f32, void *x, void *y, void *ax,

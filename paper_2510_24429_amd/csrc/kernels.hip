@@ -785,6 +785,12 @@ __device__ double kkt_w(const double *S, double w) {
     return sqrt(w * w * S[S_SP2] + S[S_SD2] / (w * w) + S[S_SG] * S[S_SG]);
 }
 
+// The measure a solve stops on and picks its candidate by: maxresid, or for
+// a feasibility phase the relative primal (1) or dual (2) residual alone.
+__device__ double stop_metric(const State *st, const double *S) {
+    return st->stop_on == 1 ? S[S_RELP] : st->stop_on == 2 ? S[S_RELD] : S[S_MAXR];
+}
+
 // Primal weight at a restart from the distances dx, dy travelled since the
 // previous restart: smoothing toward dy / dx in log space (omega_rule 0), or
 // PID control of log omega on the error e = log(omega dx / dy) (rule 1).
@@ -883,6 +889,7 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
     st->copy_avg = 0;
     st->set_last = 0;
     st->snap_n = 0;
+    st->polish_due = 0;
 
     if (st->variant == 1) {
         // reflected Halpern: candidate 1 is T(z); z itself is not projected,
@@ -914,7 +921,7 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
                 st->snap_n = fired;
                 st->snap_cand = 1;
             }
-            if (mrb <= st->eps_rel) {
+            if (stop_metric(st, st->stats[1]) <= st->eps_rel) {
                 st->status = PDHG_CONVERGED;
                 st->returned_cand = 1;
                 st->copy_pending = 1;
@@ -922,6 +929,10 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
             } else if (initial) {
                 st->K_last = r_cur;
             } else {
+                // a polishing attempt is decided on T(z) before a restart
+                st->polish_due = st->polish && st->stats[1][S_RELG] <= st->eps_rel &&
+                                 k >= st->next_polish;
+                st->polish_cand = 1;
                 const bool r = (r_cur <= st->beta_suff * st->K_last) ||
                                (r_cur <= st->beta_nec * st->K_last && r_cur > st->K_prev) ||
                                ((double)t >= st->beta_art * (double)k);
@@ -959,7 +970,8 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
         return;
     }
 
-    const int best = (ncand > 1 && st->stats[1][S_MAXR] < st->stats[0][S_MAXR]) ? 1 : 0;
+    const int best = (ncand > 1 && stop_metric(st, st->stats[1]) <
+                                       stop_metric(st, st->stats[0])) ? 1 : 0;
     double Kcur = kkt_w(st->stats[0], om);
     double Kavg = ncand > 1 ? kkt_w(st->stats[1], om) : INFINITY;
     int restarted = 0, cand = (Kavg < Kcur) ? 1 : 0;
@@ -987,7 +999,7 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
             st->snap_n = fired;
             st->snap_cand = best;
         }
-        if (mrb <= st->eps_rel) {
+        if (stop_metric(st, st->stats[best]) <= st->eps_rel) {
             st->status = PDHG_CONVERGED;
             st->returned_cand = best;
             if (best == 1) {
@@ -995,6 +1007,11 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
                 st->copy_avg = 1;
             }
         } else if (!initial) {
+            // a polishing attempt is decided on the better candidate before
+            // the restart test may replace it
+            st->polish_due = st->polish && st->stats[best][S_RELG] <= st->eps_rel &&
+                             k >= st->next_polish;
+            st->polish_cand = best;
             const double *S = st->stats[cand];
             const double Kc = cand ? Kavg : Kcur;
             const bool r = (Kc <= st->beta_suff * st->K_last) ||
@@ -1030,6 +1047,21 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
         e[7] = om;
         ++st->n_log;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_polish_stash(
+    const State *st, const T *x0, const T *y0, const T *x1, const T *y1,
+    const double *dr, const double *dc, double *xs, double *ys, int64_t m,
+    int64_t n) {
+    if (!st->polish_due) return;
+    const T *x = st->polish_cand ? x1 : x0;
+    const T *y = st->polish_cand ? y1 : y0;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < n; j += stride)
+        xs[j] = dc[j] * (double)x[j];
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m; i += stride)
+        ys[i] = dr[i] * (double)y[i];
 }
 
 __global__ void k_advance(State *st, int batch) {
@@ -1137,6 +1169,22 @@ void launch_control(State *st, const double *partial, int ncand, int batch,
                     int initial, double *log, hipStream_t s) {
     hipLaunchKernelGGL(k_control, dim3(1), dim3(kWG), 0, s, st, partial,
                        ncand, batch, initial, log);
+}
+
+void launch_polish_stash(const State *st, bool f32, const void *x0,
+                         const void *y0, const void *x1, const void *y1,
+                         const double *dr, const double *dc, double *xs,
+                         double *ys, int64_t m, int64_t n, hipStream_t s) {
+    const int g = grid_for(n > m ? n : m, kWG, 4096);
+    if (f32)
+        hipLaunchKernelGGL(k_polish_stash<float>, dim3(g), dim3(kWG), 0, s, st,
+                           (const float *)x0, (const float *)y0, (const float *)x1,
+                           (const float *)y1, dr, dc, xs, ys, m, n);
+    else
+        hipLaunchKernelGGL(k_polish_stash<double>, dim3(g), dim3(kWG), 0, s, st,
+                           (const double *)x0, (const double *)y0,
+                           (const double *)x1, (const double *)y1, dr, dc, xs,
+                           ys, m, n);
 }
 
 void launch_advance(State *st, int batch, hipStream_t s) {

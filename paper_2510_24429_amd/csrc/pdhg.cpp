@@ -110,6 +110,16 @@ struct pdhg_ctx {
     float *bh32 = nullptr, *ch32 = nullptr, *lh32 = nullptr;
     double *xo = nullptr, *yo = nullptr;  // outer FP64 iterate (scaled)
 
+    // feasibility polishing: the candidate set aside (unscaled), the phase
+    // results (scaled), zero data vectors, and the main solve's iterate
+    double *pol_x = nullptr, *pol_y = nullptr, *pol_xp = nullptr, *pol_yd = nullptr;
+    double *zero_n = nullptr, *zero_m = nullptr;
+    float *zero_n32 = nullptr, *zero_m32 = nullptr;
+    Iter<double> bk64;
+    Iter<float> bk32;
+    int polish_attempts = 0;
+    int64_t polish_iters = 0;
+
     // active problem of the current solve
     const double *act_bs = nullptr, *act_cs = nullptr, *act_ls = nullptr;
     bool act_has_l = false;
@@ -331,6 +341,12 @@ void free_problem(pdhg_ctx *c) {
     dfree(c->lh32);
     dfree(c->xo);
     dfree(c->yo);
+    for (double **p : {&c->pol_x, &c->pol_y, &c->pol_xp, &c->pol_yd, &c->zero_n, &c->zero_m})
+        dfree(*p);
+    dfree(c->zero_n32);
+    dfree(c->zero_m32);
+    free_iter(c->bk64);
+    free_iter(c->bk32);
     free_iter(c->v64);
     free_iter(c->v32);
     dfree(c->aty_cur);
@@ -564,6 +580,9 @@ State fresh_state(pdhg_ctx *c, double omega, double nb, double nc) {
     s.pid_kd = c->params.pid_kd;
     s.pid_int = 0.0;
     s.pid_eprev = 0.0;
+    s.stop_on = c->params.stop_on;
+    s.polish = c->params.polish;
+    s.next_polish = 0;
     s.variant = c->params.variant;
     s.reflect = c->params.reflect;
     s.status = PDHG_RUNNING;
@@ -651,6 +670,9 @@ void enqueue_eval(pdhg_ctx *c, int batch, bool initial) {
         launch_snapshot_pack(c->st, h, x0, y0, x1, y1, c->aty_cur, c->aty_avg,
                              c->act_cs, c->dr, c->dc, c->pr, c->pc, c->slots,
                              c->m, c->n, c->stream);
+    if (c->params.polish)
+        launch_polish_stash(c->st, h, x0, y0, x1, y1, c->dr, c->dc, c->pol_x,
+                            c->pol_y, c->m, c->n, c->stream);
     if (h)
         launch_restart_apply(c->st, true, c->v32.x, c->v32.y, c->v32.ax,
                              c->v32.xbar, c->v32.ybar, c->ax_avg, c->v32.xl,
@@ -860,8 +882,11 @@ bool refine_outer_reached(pdhg_ctx *c) {
                                 : refine_outer_reached_T(c, c->v32);
 }
 
-// The iteration loop shared by pdhg_iterate and the refinement's inner
-// solves.  Runs until the status leaves RUNNING or `max_more` iterations.
+void polish(pdhg_ctx *c);
+
+// The iteration loop shared by pdhg_iterate, the refinement's inner solves
+// and the polishing phases.  Runs until the status leaves RUNNING or
+// `max_more` iterations.
 int run_iterations(pdhg_ctx *c, int64_t max_more, int64_t limit_total) {
     if (!c->initial_done) {
         c->t_start = now_s();
@@ -901,6 +926,7 @@ int run_iterations(pdhg_ctx *c, int64_t max_more, int64_t limit_total) {
             c->status = c->st_host->status;
             c->k_host = c->st_host->k;
             collect_snapshots(c);
+            if (c->status == PDHG_RUNNING && c->st_host->polish_due) polish(c);
             if (c->status == PDHG_RUNNING && c->ref_target >= 0.0 &&
                 refine_outer_reached(c)) {
                 launch_set_status(c->st, PDHG_CONVERGED, c->stream);
@@ -1233,6 +1259,181 @@ int pdhg_set_rhs_obj(pdhg_ctx *c, const double *b, const double *cv, int mem) {
     API_END(c)
 }
 
+}  // extern "C"
+
+namespace {
+
+// The start of a solve from the scaled FP64 pair (xo, yo): iterate, restart
+// point, A~x and the Halpern anchor in the active precision.
+void start_iterate(pdhg_ctx *c) {
+    if (f32(c)) {
+        zero_iter(c, c->v32);
+        launch_to_f32(c->v32.x, c->xo, c->n, c->stream);
+        launch_to_f32(c->v32.y, c->yo, c->m, c->stream);
+        HIPC(hipMemcpyAsync(c->v32.xl, c->v32.x, c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v32.yl, c->v32.y, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
+        HIPC(hipMemcpyAsync(c->v32.ax0, c->v32.ax, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        zero_iter(c, c->v64);
+        HIPC(hipMemcpyAsync(c->v64.x, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v64.y, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v64.xl, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->v64.yl, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        spmv_f64(c->A, c->A.v64, c->v64.x, c->v64.ax, c->stream);
+        HIPC(hipMemcpyAsync(c->v64.ax0, c->v64.ax, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+}
+
+template <typename T>
+void copy_iter(pdhg_ctx *c, Iter<T> &dst, const Iter<T> &src) {
+    const size_t n = c->n * sizeof(T), m = c->m * sizeof(T);
+    for (auto pr : {std::make_pair(dst.x, src.x), std::make_pair(dst.xbar, src.xbar),
+                    std::make_pair(dst.xl, src.xl)})
+        HIPC(hipMemcpyAsync(pr.first, pr.second, n, hipMemcpyDeviceToDevice, c->stream));
+    for (auto pr : {std::make_pair(dst.y, src.y), std::make_pair(dst.ybar, src.ybar),
+                    std::make_pair(dst.yl, src.yl), std::make_pair(dst.ax, src.ax),
+                    std::make_pair(dst.ax0, src.ax0)})
+        HIPC(hipMemcpyAsync(pr.first, pr.second, m, hipMemcpyDeviceToDevice, c->stream));
+}
+
+// One feasibility polishing attempt (see pdhg_iterate), called by the
+// iteration loop after an evaluation that asked for it; the candidate waits
+// unscaled in pol_x / pol_y.  The main solve (iterate, control state, host
+// bookkeeping) is set aside, the two phases run as solves of their own on
+// the same scaled matrix, and the main solve comes back either converged
+// at the polished pair or unchanged with its next polishing point at 2k.
+void polish(pdhg_ctx *c) {
+    const State main_st = *c->st_host;
+    const int64_t k = main_st.k, E = c->params.eval_every;
+    int64_t budget = (int64_t)std::ceil(c->params.polish_frac * (double)k / (double)E) * E;
+    if (budget < E) budget = E;
+    const bool h = f32(c);
+    if (h) {
+        alloc_iter(c->bk32, c->m, c->n);
+        copy_iter(c, c->bk32, c->v32);
+    } else {
+        alloc_iter(c->bk64, c->m, c->n);
+        copy_iter(c, c->bk64, c->v64);
+    }
+    const pdhg_params saved = c->params;
+    const std::vector<double> saved_levels = c->levels;
+    const int saved_slots = c->n_slots;
+    const bool saved_initial = c->initial_done, saved_keep = c->keep_snaps;
+    const double saved_t_start = c->t_start, saved_t_iter = c->t_iter;
+    c->keep_snaps = true;
+    c->levels.clear();
+    c->n_slots = 0;
+    c->params.polish = 0;
+    c->params.n_levels = 0;
+    c->params.literal_snapshots = 0;
+    c->params.max_iters = budget;
+    int64_t used = 0;
+    // one phase from the scaled start (xo, yo): a solve of its own that stops
+    // on rel_p (mode 1) or rel_d (mode 2), logging nothing
+    auto phase = [&](int mode) {
+        start_iterate(c);
+        State s = fresh_state(c, main_st.omega, mode == 1 ? c->nb : 0.0,
+                              mode == 1 ? 0.0 : c->nc);
+        s.stop_on = mode;
+        s.log_cap = 0;
+        write_state(c, s);
+        *c->st_host = s;
+        c->initial_done = false;
+        c->k_host = 0;
+        c->status = PDHG_RUNNING;
+        run_iterations(c, budget, budget);
+        used += c->k_host;
+        return c->status == PDHG_CONVERGED;
+    };
+    bool ok = false;
+    // primal phase: min 0 s.t. A~x = b~, x >= l~, from (x, 0)
+    c->act_bs = c->bs;
+    c->act_cs = c->zero_n;
+    c->act_ls = c->ls;
+    c->act_has_l = c->has_l;
+    c->v64.bs = c->bs;
+    c->v64.cs = c->zero_n;
+    c->v64.ls = c->ls;
+    c->v32.bs = c->bs32;
+    c->v32.cs = c->zero_n32;
+    c->v32.ls = c->ls32;
+    launch_ew(c->xo, c->pol_x, c->dc, c->n, 1, c->stream);
+    launch_fill(c->yo, 0.0, c->m, c->stream);
+    if (phase(1)) {
+        if (h)
+            launch_to_f64(c->pol_xp, c->v32.x, c->n, c->stream);
+        else
+            HIPC(hipMemcpyAsync(c->pol_xp, c->v64.x, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        // dual phase: min c~^T x s.t. A~x = 0, x >= 0, from (0, y)
+        c->act_bs = c->zero_m;
+        c->act_cs = c->cs;
+        c->act_ls = c->zero_n;
+        c->act_has_l = false;
+        c->v64.bs = c->zero_m;
+        c->v64.cs = c->cs;
+        c->v64.ls = c->zero_n;
+        c->v32.bs = c->zero_m32;
+        c->v32.cs = c->cs32;
+        c->v32.ls = c->zero_n32;
+        launch_fill(c->xo, 0.0, c->n, c->stream);
+        launch_ew(c->yo, c->pol_y, c->dr, c->m, 1, c->stream);
+        if (phase(2)) {
+            if (h)
+                launch_to_f64(c->pol_yd, c->v32.y, c->m, c->stream);
+            else
+                HIPC(hipMemcpyAsync(c->pol_yd, c->v64.y, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            pdhg_kkt K;
+            kkt_pair64(c, c->pol_xp, c->pol_yd, c->bs, c->cs, c->has_l ? c->ls : nullptr,
+                       c->nb, c->nc, &K);
+            ok = K.maxresid <= saved.eps_rel;
+        }
+    }
+    // the main solve back
+    c->params = saved;
+    c->levels = saved_levels;
+    c->n_slots = saved_slots;
+    configure_solve_state(c);
+    if (h)
+        copy_iter(c, c->v32, c->bk32);
+    else
+        copy_iter(c, c->v64, c->bk64);
+    c->initial_done = saved_initial;
+    c->keep_snaps = saved_keep;
+    c->t_start = saved_t_start;
+    c->t_iter = saved_t_iter;
+    c->polish_attempts += 1;
+    c->polish_iters += used;
+    State s = main_st;
+    s.polish_due = 0;
+    if (ok) {
+        // the polished pair becomes the returned iterate
+        if (h) {
+            launch_to_f32(c->v32.x, c->pol_xp, c->n, c->stream);
+            launch_to_f32(c->v32.y, c->pol_yd, c->m, c->stream);
+            spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
+        } else {
+            HIPC(hipMemcpyAsync(c->v64.x, c->pol_xp, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPC(hipMemcpyAsync(c->v64.y, c->pol_yd, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            spmv_f64(c->A, c->A.v64, c->v64.x, c->v64.ax, c->stream);
+        }
+        s.status = PDHG_CONVERGED;
+        s.returned_cand = 2;
+        s.copy_pending = 0;
+        s.snap_n = 0;
+    } else {
+        s.next_polish = 2 * k;
+    }
+    write_state(c, s);
+    *c->st_host = s;
+    c->status = s.status;
+    c->k_host = s.k;
+}
+
+}  // namespace
+
+extern "C" {
+
 int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
     API_BEGIN(c)
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
@@ -1243,7 +1444,9 @@ int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
         (p->precision != PDHG_FP64 && p->precision != PDHG_FP32) ||
         !(p->eps_rel >= 0.0) || p->max_iters < 0 ||
         (p->variant != 0 && p->variant != 1) || !(p->reflect >= 0.0 && p->reflect <= 1.0) ||
-        (p->omega_rule != 0 && p->omega_rule != 1))
+        (p->omega_rule != 0 && p->omega_rule != 1) ||
+        p->stop_on < 0 || p->stop_on > 2 || (p->polish != 0 && p->polish != 1) ||
+        (p->polish && !(p->polish_frac > 0.0)))
         return fail(c, PDHG_E_ARG, "invalid parameters");
     for (int i = 1; i < p->n_levels; ++i)
         if (!(p->levels[i] < p->levels[i - 1]))
@@ -1263,6 +1466,22 @@ int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
         c->n_slots = (int)c->levels.size();
         c->slots = dmalloc<double>((int64_t)c->n_slots * (2 * c->n + c->m));
     }
+    if (p->polish && !c->pol_x) {
+        c->pol_x = dmalloc<double>(c->n);
+        c->pol_y = dmalloc<double>(c->m);
+        c->pol_xp = dmalloc<double>(c->n);
+        c->pol_yd = dmalloc<double>(c->m);
+        c->zero_n = dmalloc<double>(c->n);
+        c->zero_m = dmalloc<double>(c->m);
+        c->zero_n32 = dmalloc<float>(c->n);
+        c->zero_m32 = dmalloc<float>(c->m);
+        launch_fill(c->zero_n, 0.0, c->n, c->stream);
+        launch_fill(c->zero_m, 0.0, c->m, c->stream);
+        launch_fill32(c->zero_n32, 0.0f, c->n, c->stream);
+        launch_fill32(c->zero_m32, 0.0f, c->m, c->stream);
+    }
+    c->polish_attempts = 0;
+    c->polish_iters = 0;
     ruiz(c, p->ruiz_passes);
     apply_scaling(c);
     apply_rhs_scaling(c);
@@ -1309,23 +1528,9 @@ int pdhg_set_iterate(pdhg_ctx *c, const double *x, const double *y, int mem) {
     } else {
         launch_fill(c->yo, 0.0, c->m, c->stream);
     }
-    if (f32(c)) {
-        zero_iter(c, c->v32);
-        launch_to_f32(c->v32.x, c->xo, c->n, c->stream);
-        launch_to_f32(c->v32.y, c->yo, c->m, c->stream);
-        HIPC(hipMemcpyAsync(c->v32.xl, c->v32.x, c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-        HIPC(hipMemcpyAsync(c->v32.yl, c->v32.y, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-        spmv_f32(c->A, c->v32.x, c->v32.ax, c->stream);
-        HIPC(hipMemcpyAsync(c->v32.ax0, c->v32.ax, c->m * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-    } else {
-        zero_iter(c, c->v64);
-        HIPC(hipMemcpyAsync(c->v64.x, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        HIPC(hipMemcpyAsync(c->v64.y, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        HIPC(hipMemcpyAsync(c->v64.xl, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        HIPC(hipMemcpyAsync(c->v64.yl, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        spmv_f64(c->A, c->A.v64, c->v64.x, c->v64.ax, c->stream);
-        HIPC(hipMemcpyAsync(c->v64.ax0, c->v64.ax, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    }
+    start_iterate(c);
+    c->polish_attempts = 0;
+    c->polish_iters = 0;
     write_state(c, c->st_init);
     *c->st_host = c->st_init;
     reset_solve(c);
@@ -1369,6 +1574,8 @@ int pdhg_get_info(pdhg_ctx *c, pdhg_info *o) {
     o->sigma = s.sigma;
     o->t_setup = c->t_setup;
     o->t_iter = c->t_iter;
+    o->polish_attempts = c->polish_attempts;
+    o->polish_iters = c->polish_iters;
     kkt_of(c, 0, &o->kkt);
     return PDHG_OK;
     API_END(c)
@@ -1719,6 +1926,8 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
         c->n_slots = 0;
         c->params.eps_rel = R.inner_eps;
         c->params.max_iters = R.max_inner_iters;
+        c->params.polish = 0;           // the inner solves do not polish
+        c->params.stop_on = 0;
         for (r = 0;; ++r) {
             // outer FP64 KKT of (xo, yo) on the original problem
             kkt_pair64(c, xo, yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);

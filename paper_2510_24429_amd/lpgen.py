@@ -281,6 +281,23 @@ def planted_coupled(m: int = 5_000_000, n: int = 20_000_000, k: int = 5,
                         seed=seed))
 
 
+def planted_flat(m: int = 300, n: int = 1000, k: int = 5, seed: int = 1) -> LP:
+    """The uniform pattern with c = A^T y* (no reduced costs): c^T x = y*^T b
+    on the whole feasible set, so every feasible point is optimal.  b = A x*
+    with x* ~ U(0.1, 1) strictly positive."""
+    base = planted_uniform(m=m, n=n, k=k, seed=seed)
+    rows = np.repeat(np.arange(m), np.diff(base.a_rp))
+    cols = base.a_ci.astype(np.int64)
+    rng = np.random.default_rng(seed + 100)
+    x = rng.uniform(0.1, 1.0, n)
+    y = rng.standard_normal(m)
+    b = np.bincount(rows, weights=base.a_v * x[cols], minlength=m)
+    c = np.bincount(cols, weights=base.a_v * y[rows], minlength=n)
+    arrs = _csr_pair(m, n, rows, cols, base.a_v)
+    return LP(m, n, *arrs, b=b, c=c, x_star=x, y_star=y, z_star=np.zeros(n),
+              name="flat", meta=dict(family="flat", k=k, seed=seed))
+
+
 def tiny_dense(m: int, n: int, seed: int, density: float = 1.0) -> LP:
     """Small LP (dense or sparse pattern) with a planted optimum."""
     rng = np.random.default_rng(seed)

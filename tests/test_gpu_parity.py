@@ -344,3 +344,64 @@ def test_full_size_powerlaw_parity(Solver, oracle):
         assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
         assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0,
                            equal_nan=True)
+
+
+# ------------------------------------------------- feasibility polishing
+
+def _solve_pair(Solver, oracle, lp, **kw):
+    ref = oracle.solve(lp, **kw)
+    s = Solver.from_lp(lp)
+    s.configure(**kw)
+    st = s.solve()
+    return ref, s, st
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_feasibility_stop_measures_match_oracle(Solver, oracle, mode):
+    lp = lpgen.make("uniform_m500_n1k")
+    ref, s, st = _solve_pair(Solver, oracle, lp, eps_rel=1e-6, stop_on=mode)
+    inf = s.info()
+    assert st == 1 and ref.info["status"] == 1
+    assert inf["iters"] == ref.info["iters"] and inf["restarts"] == ref.info["restarts"]
+    key = "rel_p" if mode == 1 else "rel_d"
+    assert inf["kkt"][key] <= 1e-6
+    assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_failed_polishing_leaves_the_solve_unchanged(Solver, oracle, variant):
+    # attempts that fail must not alter the main iteration; their count and
+    # phase iterations match the oracle's
+    lp = lpgen.planted_powerlaw(m=1500, n=6000, kmax=600, seed=3)
+    ref, s, st = _solve_pair(Solver, oracle, lp, eps_rel=1e-6, variant=variant, polish=1)
+    inf = s.info()
+    assert st == 1 and ref.info["status"] == 1
+    assert inf["polish_attempts"] == ref.info["polish_attempts"] >= 1
+    assert inf["polish_iters"] == ref.info["polish_iters"]
+    assert inf["candidate"] != 2
+    assert inf["iters"] == ref.info["iters"] and inf["restarts"] == ref.info["restarts"]
+    for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
+        assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
+    with Solver.from_lp(lp) as s0:
+        s0.configure(eps_rel=1e-6, variant=variant)
+        assert s0.solve() == 1
+        assert s0.info()["iters"] == inf["iters"]
+    s.close()
+
+
+def test_polishing_success_matches_oracle(Solver, oracle):
+    lp = lpgen.planted_flat(300, 1000, 5, 1)
+    ref, s, st = _solve_pair(Solver, oracle, lp, eps_rel=1e-8, variant=0, polish=1)
+    inf = s.info()
+    assert st == 1 and ref.info["candidate"] == 2 and inf["candidate"] == 2
+    assert inf["iters"] == ref.info["iters"]
+    assert inf["polish_attempts"] == ref.info["polish_attempts"]
+    assert inf["polish_iters"] == ref.info["polish_iters"]
+    for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
+        assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
+    x, y, _ = s.get_iterate()
+    assert rel(x, ref.x) <= 1e-10 and rel(y, ref.y) <= 1e-10
+    kk = oracle.kkt(lp, x, y)
+    assert kk["maxresid"] <= 1e-8
+    s.close()

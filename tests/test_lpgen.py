@@ -72,3 +72,11 @@ def test_seeded_reproducible():
     a = lpgen.make("uniform_m500_n1k")
     b = lpgen.make("uniform_m500_n1k")
     assert np.array_equal(a.a_v, b.a_v) and np.array_equal(a.b, b.b)
+
+
+def test_planted_flat_has_cost_in_the_row_space():
+    lp = lpgen.planted_flat(200, 700, 5, 3)
+    A = lp.dense()
+    assert np.allclose(A @ lp.x_star, lp.b, rtol=1e-12, atol=1e-12)
+    assert np.allclose(A.T @ lp.y_star, lp.c, rtol=1e-12, atol=1e-12)
+    assert np.all(lp.x_star > 0)

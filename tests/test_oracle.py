@@ -459,20 +459,6 @@ def test_pid_rule_reaches_the_same_optimum(oracle):
 
 # ---------------------------------------------------------- polishing
 
-def _flat_lp(m, n, k, seed):
-    """c = A^T y* with z* = 0: c^T x = y*^T b on the whole feasible set, so
-    every feasible point is optimal and fixing feasibility cannot cost gap."""
-    base = lpgen.planted_uniform(m=m, n=n, k=k, seed=seed)
-    rows = np.repeat(np.arange(m), np.diff(base.a_rp))
-    cols = base.a_ci.astype(np.int64)
-    rng = np.random.default_rng(seed + 100)
-    x = rng.uniform(0.1, 1.0, n)
-    y = rng.standard_normal(m)
-    b = np.bincount(rows, weights=base.a_v * x[cols], minlength=m)
-    c = np.bincount(cols, weights=base.a_v * y[rows], minlength=n)
-    return lpgen.from_coo(m, n, rows, cols, base.a_v, b, c, name="flat")
-
-
 @pytest.mark.parametrize("mode", [1, 2])
 def test_feasibility_stop_measures(oracle, mode):
     # stop_on = 1 (2) stops on rel_p (rel_d) alone: the returned point meets
@@ -501,7 +487,7 @@ def test_polishing_never_alters_the_main_iteration(oracle, variant):
 
 
 def test_polishing_succeeds_when_feasibility_is_free(oracle):
-    lp = _flat_lp(300, 1000, 5, 1)
+    lp = lpgen.planted_flat(300, 1000, 5, 1)
     a = oracle.solve(lp, eps_rel=1e-8, variant=0)
     b = oracle.solve(lp, eps_rel=1e-8, variant=0, polish=1)
     assert b.info["status"] == 1 and b.info["candidate"] == 2
