@@ -282,8 +282,17 @@ def cpu_baseline(lp, iters, variant):
     print(f"[bench] cpu oracle: {r.info['iters']} iters in {r.info['t_iter']:.2f}s "
           f"(setup {r.info['t_setup']:.2f}s, wall {wall:.1f}s)", file=sys.stderr,
           flush=True)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(ips, 3), "unit": "iters/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "host_cpus": os.cpu_count(),
             "sample": f"{r.info['iters']} PDHG iterations of the same LP incl. "
                       f"evaluations at k=0 and every 64, setup excluded, 1 thread"}
 
