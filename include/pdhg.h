@@ -427,7 +427,10 @@ int pdhg_spmv(pdhg_ctx *ctx, int which, int scaled, int precision,
  *      SpMV side runs as P column panels, each on the workgroups of 8 / P of
  *      the 8 XCDs, so that each XCD's L2 holds its panel's part of the
  *      table; rows are summed over the panels in panel order, so results stay
- *      deterministic but round differently from P = 1.
+ *      deterministic but round differently from P = 1;
+ *  "stream_nt": 1 streams the CSR arrays with non-temporal loads, 0 with
+ *      plain loads, -1 (default) chooses per side: non-temporal when the
+ *      FP64 gather table per XCD (8 cols / P bytes) exceeds 3 MiB.
  * Returns PDHG_E_ARG for an unknown key or a value out of range. */
 int pdhg_set_tuning(pdhg_ctx *ctx, const char *key, int64_t value);
 /* Row-block statistics of matrix which (0 = A, 1 = A^T): counts of blocks

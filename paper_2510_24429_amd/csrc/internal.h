@@ -99,6 +99,7 @@ struct DevCsr {
     // column panels (P > 1): the stacked panel matrix (P * rows rows, its
     // values kept equal to v64 / v32 through src), and the partial sums
     int P = 1;
+    int stream_nt = 0;          // non-temporal streamed loads (see kernels)
     DevCsr *pan = nullptr;
     int32_t *pan_src = nullptr;
     double *q64 = nullptr;

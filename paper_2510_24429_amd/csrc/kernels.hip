@@ -21,9 +21,19 @@ namespace {
 
 constexpr int kFixThreads = 64;
 
-template <typename T>
-__device__ __forceinline__ T ntload(const T *p) {
-    return __builtin_nontemporal_load(p);
+// Loads of the streamed CSR arrays (indices and values, each read once per
+// SpMV), plain or non-temporal.  Measured on MI355X: plain loads are faster
+// while the gathered table fits comfortably in L2 (9.4M streamed pairs with
+// one random gather each from a 1.6 MB table: 45.5 us plain, 54.6 us
+// non-temporal; the power-law steps 7,120 -> 7,773 iterations/s), while
+// non-temporal loads keep a 5 MB gather panel in L2 (multicommodity, FP32:
+// 3,858 plain, 4,411 non-temporal).  Each matrix side picks one at load.
+template <bool NT, typename T>
+__device__ __forceinline__ T sload(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -32,17 +42,20 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Four consecutive streamed entries starting at a multiple of 4, as 16-byte
 // loads (index arrays and value arrays are padded to a multiple of 4).
+template <bool NT>
 __device__ __forceinline__ void ld4(const int32_t *p, int (&o)[4]) {
-    const v4i v = __builtin_nontemporal_load((const v4i *)p);
+    const v4i v = sload<NT>((const v4i *)p);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
+template <bool NT>
 __device__ __forceinline__ void ld4(const double *p, double (&o)[4]) {
-    const v2d a = __builtin_nontemporal_load((const v2d *)p);
-    const v2d b = __builtin_nontemporal_load((const v2d *)(p + 2));
+    const v2d a = sload<NT>((const v2d *)p);
+    const v2d b = sload<NT>((const v2d *)(p + 2));
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
+template <bool NT>
 __device__ __forceinline__ void ld4(const float *p, float (&o)[4]) {
-    const v4f v = __builtin_nontemporal_load((const v4f *)p);
+    const v4f v = sload<NT>((const v4f *)p);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
 
@@ -82,24 +95,26 @@ __device__ __forceinline__ double block_max(double v, double *sred) {
 
 // ---------------------------------------------------------------- elements
 
-// One nonzero's contribution v[p] * x[ci[p]].  fetch() reads the streamed
-// index and value (non-temporal: they are used once), apply() gathers x and
-// multiplies; splitting the two lets a thread issue all of its index/value
-// loads, then all of its gathers, before waiting on any of them.
+// One nonzero's contribution v[p] * x[ci[p]].  fetch4() reads four streamed
+// indices and values, apply() gathers x and multiplies; splitting the two
+// lets a thread issue all of its index/value loads, then all of its gathers,
+// before waiting on any of them.
 template <typename MT, typename VT, typename Acc>
 struct SpmvElem {
     const int32_t *ci;
     const MT *v;
     const VT *x;
-    __device__ __forceinline__ void fetch(int p, int &j, MT &a) const {
-        j = ntload(ci + p);
-        a = ntload(v + p);
-    }
+    int nt;                     // non-temporal streamed loads (uniform)
     // entries base..base+3 (base a multiple of 4)
     __device__ __forceinline__ void fetch4(int base, int (&j)[4],
                                            MT (&a)[4]) const {
-        ld4(ci + base, j);
-        ld4(v + base, a);
+        if (nt) {
+            ld4<true>(ci + base, j);
+            ld4<true>(v + base, a);
+        } else {
+            ld4<false>(ci + base, j);
+            ld4<false>(v + base, a);
+        }
     }
     __device__ __forceinline__ Acc apply(int j, MT a) const {
         return (Acc)a * (Acc)x[j];
@@ -516,7 +531,7 @@ void rb_spmv(const DevCsr &M, const MT *vals, const VT *in, Epi e,
         }
     }
     if (!tv) {
-        run_bins<Acc>(M, SpmvElem<MT, VT, Acc>{M.ci, vals, in}, e, s);
+        run_bins<Acc>(M, SpmvElem<MT, VT, Acc>{M.ci, vals, in, M.stream_nt}, e, s);
         return;
     }
     Acc *q;
@@ -524,7 +539,7 @@ void rb_spmv(const DevCsr &M, const MT *vals, const VT *in, Epi e,
         q = M.q64;
     else
         q = M.q32;
-    run_bins<Acc>(*M.pan, SpmvElem<MT, VT, Acc>{M.pan->ci, tv, in},
+    run_bins<Acc>(*M.pan, SpmvElem<MT, VT, Acc>{M.pan->ci, tv, in, M.stream_nt},
                   PanelEpi<Epi, Acc>{e, q}, s);
     hipLaunchKernelGGL((k_panel_combine<Acc, Epi>),
                        dim3(grid_for(M.rows, kWG, 4096)), dim3(kWG), 0, s, q,

@@ -100,6 +100,7 @@ struct pdhg_ctx {
     int64_t split_threshold = (int64_t)1 << 20;
     int64_t split_chunk = (int64_t)1 << 16;
     int panels_a = 0, panels_at = 0;    // column panels per side; 0 = choose
+    int stream_nt = -1;                 // streamed-load kind; -1 = choose
 
     // scaling and scaled data
     double *dr = nullptr, *dc = nullptr;
@@ -456,6 +457,10 @@ void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
     upload_bins(M, build_row_blocks(rows, rp.data(), kTile64 - 3, c->split_threshold, c->split_chunk),
                 build_row_blocks(rows, rp.data(), kTile32 - 3, c->split_threshold, c->split_chunk));
     if (P > 1) upload_panels(c, M, rp, ci, P, cut);
+    // stream the CSR non-temporally when the FP64 gather table each XCD
+    // works on exceeds 3 MiB, so that streaming does not evict it from L2
+    M.stream_nt = c->stream_nt >= 0 ? c->stream_nt
+                                    : (8.0 * (double)cols / P > 3.0 * 1048576.0);
 }
 
 template <typename T>
@@ -1133,6 +1138,10 @@ int pdhg_set_tuning(pdhg_ctx *c, const char *key, int64_t value) {
     }
     if (std::strcmp(key, "panels_at") == 0 && pv) {
         c->panels_at = (int)value;
+        return PDHG_OK;
+    }
+    if (std::strcmp(key, "stream_nt") == 0 && value >= -1 && value <= 1) {
+        c->stream_nt = (int)value;
         return PDHG_OK;
     }
     return fail(c, PDHG_E_ARG, "unknown tuning key or value out of range");

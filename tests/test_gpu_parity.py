@@ -67,6 +67,8 @@ def test_spmv_bins_bitwise_on_integers(Solver, split, panels):
     tuning = {"split_threshold": 4096, "split_chunk": 1000} if split else {}
     if panels:
         tuning.update(PANELS)
+    # both streamed-load kinds: non-temporal with panels, plain without
+    tuning["stream_nt"] = 1 if panels else 0
     s = Solver.from_lp(lp, tuning=tuning)
     assert (s.panel_count(0), s.panel_count(1)) == ((4, 8) if panels else (1, 1))
     st = s.bin_stats(0)
