@@ -27,7 +27,7 @@ constexpr int kFixThreads = 64;
 // one random gather each from a 1.6 MB table: 45.5 us plain, 54.6 us
 // non-temporal; the power-law steps 7,120 -> 7,773 iterations/s), while
 // non-temporal loads keep a 5 MB gather panel in L2 (multicommodity, FP32:
-// 3,858 plain, 4,411 non-temporal).  Each matrix side picks one at load.
+// 3,828 plain, 4,294 non-temporal).  Each matrix side picks one at load.
 template <bool NT, typename T>
 __device__ __forceinline__ T sload(const T *p) {
     if constexpr (NT)
@@ -99,22 +99,19 @@ __device__ __forceinline__ double block_max(double v, double *sred) {
 // indices and values, apply() gathers x and multiplies; splitting the two
 // lets a thread issue all of its index/value loads, then all of its gathers,
 // before waiting on any of them.
-template <typename MT, typename VT, typename Acc>
+// (The load kind is a template parameter: a runtime branch between the two
+// kinds of otherwise identical loads was merged by the compiler into plain
+// loads.)
+template <typename MT, typename VT, typename Acc, bool NT>
 struct SpmvElem {
     const int32_t *ci;
     const MT *v;
     const VT *x;
-    int nt;                     // non-temporal streamed loads (uniform)
     // entries base..base+3 (base a multiple of 4)
     __device__ __forceinline__ void fetch4(int base, int (&j)[4],
                                            MT (&a)[4]) const {
-        if (nt) {
-            ld4<true>(ci + base, j);
-            ld4<true>(v + base, a);
-        } else {
-            ld4<false>(ci + base, j);
-            ld4<false>(v + base, a);
-        }
+        ld4<NT>(ci + base, j);
+        ld4<NT>(v + base, a);
     }
     __device__ __forceinline__ Acc apply(int j, MT a) const {
         return (Acc)a * (Acc)x[j];
@@ -531,7 +528,10 @@ void rb_spmv(const DevCsr &M, const MT *vals, const VT *in, Epi e,
         }
     }
     if (!tv) {
-        run_bins<Acc>(M, SpmvElem<MT, VT, Acc>{M.ci, vals, in, M.stream_nt}, e, s);
+        if (M.stream_nt)
+            run_bins<Acc>(M, SpmvElem<MT, VT, Acc, true>{M.ci, vals, in}, e, s);
+        else
+            run_bins<Acc>(M, SpmvElem<MT, VT, Acc, false>{M.ci, vals, in}, e, s);
         return;
     }
     Acc *q;
@@ -539,8 +539,12 @@ void rb_spmv(const DevCsr &M, const MT *vals, const VT *in, Epi e,
         q = M.q64;
     else
         q = M.q32;
-    run_bins<Acc>(*M.pan, SpmvElem<MT, VT, Acc>{M.pan->ci, tv, in, M.stream_nt},
-                  PanelEpi<Epi, Acc>{e, q}, s);
+    if (M.stream_nt)
+        run_bins<Acc>(*M.pan, SpmvElem<MT, VT, Acc, true>{M.pan->ci, tv, in},
+                      PanelEpi<Epi, Acc>{e, q}, s);
+    else
+        run_bins<Acc>(*M.pan, SpmvElem<MT, VT, Acc, false>{M.pan->ci, tv, in},
+                      PanelEpi<Epi, Acc>{e, q}, s);
     hipLaunchKernelGGL((k_panel_combine<Acc, Epi>),
                        dim3(grid_for(M.rows, kWG, 4096)), dim3(kWG), 0, s, q,
                        M.P, (int)M.rows, e);
