@@ -1355,7 +1355,23 @@ void polish(pdhg_ctx *c) {
         used += c->k_host;
         return c->status == PDHG_CONVERGED;
     };
+    // the main solve back (also when a phase throws)
+    auto restore = [&]() {
+        c->params = saved;
+        c->levels = saved_levels;
+        c->n_slots = saved_slots;
+        configure_solve_state(c);
+        if (h)
+            copy_iter(c, c->v32, c->bk32);
+        else
+            copy_iter(c, c->v64, c->bk64);
+        c->initial_done = saved_initial;
+        c->keep_snaps = saved_keep;
+        c->t_start = saved_t_start;
+        c->t_iter = saved_t_iter;
+    };
     bool ok = false;
+    try {
     // primal phase: min 0 s.t. A~x = b~, x >= l~, from (x, 0)
     c->act_bs = c->bs;
     c->act_cs = c->zero_n;
@@ -1398,19 +1414,13 @@ void polish(pdhg_ctx *c) {
             ok = K.maxresid <= saved.eps_rel;
         }
     }
-    // the main solve back
-    c->params = saved;
-    c->levels = saved_levels;
-    c->n_slots = saved_slots;
-    configure_solve_state(c);
-    if (h)
-        copy_iter(c, c->v32, c->bk32);
-    else
-        copy_iter(c, c->v64, c->bk64);
-    c->initial_done = saved_initial;
-    c->keep_snaps = saved_keep;
-    c->t_start = saved_t_start;
-    c->t_iter = saved_t_iter;
+    } catch (...) {
+        restore();
+        write_state(c, main_st);
+        *c->st_host = main_st;
+        throw;
+    }
+    restore();
     c->polish_attempts += 1;
     c->polish_iters += used;
     State s = main_st;
