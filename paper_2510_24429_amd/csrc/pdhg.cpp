@@ -1372,48 +1372,48 @@ void polish(pdhg_ctx *c) {
     };
     bool ok = false;
     try {
-    // primal phase: min 0 s.t. A~x = b~, x >= l~, from (x, 0)
-    c->act_bs = c->bs;
-    c->act_cs = c->zero_n;
-    c->act_ls = c->ls;
-    c->act_has_l = c->has_l;
-    c->v64.bs = c->bs;
-    c->v64.cs = c->zero_n;
-    c->v64.ls = c->ls;
-    c->v32.bs = c->bs32;
-    c->v32.cs = c->zero_n32;
-    c->v32.ls = c->ls32;
-    launch_ew(c->xo, c->pol_x, c->dc, c->n, 1, c->stream);
-    launch_fill(c->yo, 0.0, c->m, c->stream);
-    if (phase(1)) {
-        if (h)
-            launch_to_f64(c->pol_xp, c->v32.x, c->n, c->stream);
-        else
-            HIPC(hipMemcpyAsync(c->pol_xp, c->v64.x, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        // dual phase: min c~^T x s.t. A~x = 0, x >= 0, from (0, y)
-        c->act_bs = c->zero_m;
-        c->act_cs = c->cs;
-        c->act_ls = c->zero_n;
-        c->act_has_l = false;
-        c->v64.bs = c->zero_m;
-        c->v64.cs = c->cs;
-        c->v64.ls = c->zero_n;
-        c->v32.bs = c->zero_m32;
-        c->v32.cs = c->cs32;
-        c->v32.ls = c->zero_n32;
-        launch_fill(c->xo, 0.0, c->n, c->stream);
-        launch_ew(c->yo, c->pol_y, c->dr, c->m, 1, c->stream);
-        if (phase(2)) {
+        // primal phase: min 0 s.t. A~x = b~, x >= l~, from (x, 0)
+        c->act_bs = c->bs;
+        c->act_cs = c->zero_n;
+        c->act_ls = c->ls;
+        c->act_has_l = c->has_l;
+        c->v64.bs = c->bs;
+        c->v64.cs = c->zero_n;
+        c->v64.ls = c->ls;
+        c->v32.bs = c->bs32;
+        c->v32.cs = c->zero_n32;
+        c->v32.ls = c->ls32;
+        launch_ew(c->xo, c->pol_x, c->dc, c->n, 1, c->stream);
+        launch_fill(c->yo, 0.0, c->m, c->stream);
+        if (phase(1)) {
             if (h)
-                launch_to_f64(c->pol_yd, c->v32.y, c->m, c->stream);
+                launch_to_f64(c->pol_xp, c->v32.x, c->n, c->stream);
             else
-                HIPC(hipMemcpyAsync(c->pol_yd, c->v64.y, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            pdhg_kkt K;
-            kkt_pair64(c, c->pol_xp, c->pol_yd, c->bs, c->cs, c->has_l ? c->ls : nullptr,
-                       c->nb, c->nc, &K);
-            ok = K.maxresid <= saved.eps_rel;
+                HIPC(hipMemcpyAsync(c->pol_xp, c->v64.x, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            // dual phase: min c~^T x s.t. A~x = 0, x >= 0, from (0, y)
+            c->act_bs = c->zero_m;
+            c->act_cs = c->cs;
+            c->act_ls = c->zero_n;
+            c->act_has_l = false;
+            c->v64.bs = c->zero_m;
+            c->v64.cs = c->cs;
+            c->v64.ls = c->zero_n;
+            c->v32.bs = c->zero_m32;
+            c->v32.cs = c->cs32;
+            c->v32.ls = c->zero_n32;
+            launch_fill(c->xo, 0.0, c->n, c->stream);
+            launch_ew(c->yo, c->pol_y, c->dr, c->m, 1, c->stream);
+            if (phase(2)) {
+                if (h)
+                    launch_to_f64(c->pol_yd, c->v32.y, c->m, c->stream);
+                else
+                    HIPC(hipMemcpyAsync(c->pol_yd, c->v64.y, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                pdhg_kkt K;
+                kkt_pair64(c, c->pol_xp, c->pol_yd, c->bs, c->cs, c->has_l ? c->ls : nullptr,
+                           c->nb, c->nc, &K);
+                ok = K.maxresid <= saved.eps_rel;
+            }
         }
-    }
     } catch (...) {
         restore();
         write_state(c, main_st);
