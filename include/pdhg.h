@@ -360,6 +360,16 @@ int pdhg_concurrent_crossover(pdhg_ctx *ctx, pdhg_crossover_fn fn, void *user,
                               int max_threads, int64_t max_iters,
                               int *winner, int *status);
 
+/* Algorithm 1 over FP32 bulk iterations with FP64 refinement: as
+ * pdhg_concurrent_crossover, with pdhg_solve_refined(ctx, rp, info) (rp NULL:
+ * defaults) as the solve, whose snapshots of the refined iterate launch the
+ * crossovers; a winner stops the refinement (*status PDHG_CANCELLED). */
+int pdhg_concurrent_crossover_refined(pdhg_ctx *ctx, pdhg_crossover_fn fn,
+                                      void *user, int max_threads,
+                                      const pdhg_refine_params *rp,
+                                      int *winner, int *status,
+                                      pdhg_refine_info *info);
+
 /* ---- FP32 bulk iteration with FP64 refinement --------------------------- */
 
 /* Iterative refinement: round 0 solves the LP with the bulk iteration in

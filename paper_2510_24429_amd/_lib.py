@@ -146,6 +146,7 @@ SIGNATURES = {
     "pdhg_set_snapshot_callback": (i32, [vp, SNAP_CB, vp]),
     "pdhg_concurrent_crossover": (i32, [vp, CROSSOVER_FN, vp, i32, i64,
                                         C.POINTER(i32), C.POINTER(i32)]),
+    "pdhg_concurrent_crossover_refined": (i32, [vp, CROSSOVER_FN, vp, i32, vp, vp, vp, vp]),
     "pdhg_solve_refined": (i32, [vp, C.POINTER(RefineParams),
                                  C.POINTER(RefineInfo)]),
     "pdhg_refine_log": (i32, [vp, vp, i32, C.POINTER(i32)]),

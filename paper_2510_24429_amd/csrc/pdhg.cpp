@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -155,6 +156,8 @@ struct pdhg_ctx {
     std::atomic<int> cancel_flag{0};
     std::vector<SnapMeta> snaps;
     bool keep_snaps = false;        // refinement: inner solves keep the list
+    bool keep_cancel = false;       // refinement: inner solves keep a cancel
+    std::function<void(int)> snap_hook;   // new snapshots [arg, end) recorded
     std::vector<double> refine_log;   // 8 doubles per refinement round
     // outer-progress test of a refinement inner solve (active when set)
     const double *ref_xo = nullptr, *ref_yo = nullptr;
@@ -604,7 +607,7 @@ void reset_solve(pdhg_ctx *c) {
     c->status = PDHG_RUNNING;
     c->t_iter = 0;
     if (!c->keep_snaps) c->snaps.clear();
-    c->cancel_flag.store(0);
+    if (!c->keep_cancel) c->cancel_flag.store(0);
 }
 
 bool f32(pdhg_ctx *c) { return c->prec == PDHG_FP32; }
@@ -819,6 +822,7 @@ void collect_snapshots(pdhg_ctx *c) {
         c->snaps.push_back(sm);
     }
     start_snapshot_copies(c, before);
+    if (c->snap_hook && (int)c->snaps.size() > before) c->snap_hook(before);
 }
 
 // Snapshots [before, end) share the slot of the first: copy it to pinned host
@@ -1771,13 +1775,23 @@ int pdhg_kernel_times(pdhg_ctx *c, pdhg_kernel_time *out, int cap, int *count,
 
 // ------------------------------------------------------------ Algorithm 1
 
-int pdhg_concurrent_crossover(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
-                              int max_threads, int64_t max_iters, int *winner,
-                              int *status) {
-    API_BEGIN(c)
-    if (!fn || max_threads < 0 || max_iters < 0)
-        return fail(c, PDHG_E_ARG, "bad argument to pdhg_concurrent_crossover");
-    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+}  // extern "C"
+
+namespace {
+
+bool refine_params_ok(const pdhg_refine_params &R);
+void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *info);
+
+// Algorithm 1 (Section 3.1) around a solve: `drive` runs it and returns the
+// PDHG status; every snapshot it records (and any recorded before) launches
+// `fn` on a host thread, at most max_threads at a time (0: no limit; a
+// later snapshot waits for a free thread).  The first call to return 1 wins:
+// the others see the cancel flag, and the solve stops at its next check.
+// Without a winner, a converged solve's final iterate gets `fn` on this
+// thread unless a snapshot was taken from that same iterate.
+int crossover_harness(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
+                      int max_threads, const std::function<int()> &drive,
+                      int *winner, int *status) {
     struct Job {
         int idx;
         pdhg_snapshot_info info;
@@ -1832,20 +1846,14 @@ int pdhg_concurrent_crossover(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
         threads.emplace_back(run_job, j);
     };
     int st = c->status;
-    size_t launched = 0;
-    const int64_t target = std::min<int64_t>(c->k_host + max_iters, c->params.max_iters);
     try {
-        for (;;) {
-            // snapshots emitted so far (including the k = 0 check)
-            if (!c->initial_done) run_iterations(c, 0, target);
-            while (launched < c->snaps.size() && !cancel) {
-                launch(fetch((int)launched));
-                ++launched;
-            }
-            st = c->status;
-            if (st != PDHG_RUNNING || cancel || c->k_host >= target) break;
-            run_iterations(c, c->params.eval_every, target);
-        }
+        for (size_t i = 0; i < c->snaps.size() && !cancel; ++i) launch(fetch((int)i));
+        c->snap_hook = [&](int before) {
+            for (int i = before; i < (int)c->snaps.size() && !cancel; ++i)
+                launch(fetch(i));
+        };
+        st = drive();
+        c->snap_hook = nullptr;
         // Algorithm 1's last line: crossover from the converged iterate on
         // this thread, unless that iterate was already handed out
         if (!cancel && st == PDHG_CONVERGED &&
@@ -1860,6 +1868,7 @@ int pdhg_concurrent_crossover(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
             run_job(j);
         }
     } catch (...) {
+        c->snap_hook = nullptr;
         cancel = 1;
         for (auto &t : threads) t.join();
         throw;
@@ -1869,23 +1878,65 @@ int pdhg_concurrent_crossover(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
     if (winner) *winner = win.load();
     if (status) *status = st;
     return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_concurrent_crossover(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
+                              int max_threads, int64_t max_iters, int *winner,
+                              int *status) {
+    API_BEGIN(c)
+    if (!fn || max_threads < 0 || max_iters < 0)
+        return fail(c, PDHG_E_ARG, "bad argument to pdhg_concurrent_crossover");
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    const int64_t target = std::min<int64_t>(c->k_host + max_iters, c->params.max_iters);
+    return crossover_harness(c, fn, user, max_threads, [&]() {
+        run_iterations(c, target - c->k_host, target);
+        return c->status;
+    }, winner, status);
     API_END(c)
 }
 
-// ------------------------------------------------------------ refinement
-
-int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
-                       pdhg_refine_info *info) {
+int pdhg_concurrent_crossover_refined(pdhg_ctx *c, pdhg_crossover_fn fn,
+                                      void *user, int max_threads,
+                                      const pdhg_refine_params *rp,
+                                      int *winner, int *status,
+                                      pdhg_refine_info *info) {
     API_BEGIN(c)
+    if (!fn || max_threads < 0)
+        return fail(c, PDHG_E_ARG, "bad argument to pdhg_concurrent_crossover_refined");
     if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
     pdhg_refine_params R;
     if (rp)
         R = *rp;
     else
         pdhg_refine_params_default(&R);
-    if (R.max_rounds < 0 || R.cap_log2 < 0 || R.cap_log2 > 60 ||
-        (R.inner_precision != PDHG_FP32 && R.inner_precision != PDHG_FP64))
-        return fail(c, PDHG_E_ARG, "invalid refinement parameters");
+    if (!refine_params_ok(R)) return fail(c, PDHG_E_ARG, "invalid refinement parameters");
+    return crossover_harness(c, fn, user, max_threads, [&]() {
+        pdhg_refine_info ri;
+        refine_impl(c, R, &ri);
+        if (info) *info = ri;
+        return (int)ri.status;
+    }, winner, status);
+    API_END(c)
+}
+
+// ------------------------------------------------------------ refinement
+
+}  // extern "C"
+
+namespace {
+
+bool refine_params_ok(const pdhg_refine_params &R) {
+    return !(R.max_rounds < 0 || R.cap_log2 < 0 || R.cap_log2 > 60 ||
+             (R.inner_precision != PDHG_FP32 && R.inner_precision != PDHG_FP64));
+}
+
+// The refinement driver behind pdhg_solve_refined (R already checked);
+// throws DevError on device errors.
+void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *info) {
     const bool in64 = R.inner_precision == PDHG_FP64;
     const double *ls = c->has_l ? c->ls : nullptr;
     const double t0 = now_s();
@@ -1912,6 +1963,9 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     c->refine_log.clear();
     c->snaps.clear();
     c->keep_snaps = true;
+    // a cancel is kept across the inner solves (each would clear it)
+    c->cancel_flag.store(0);
+    c->keep_cancel = true;
     // snapshots of the refined iterate at the configured levels, taken
     // whenever its FP64 maxresid is measured (before every round and at the
     // end); levels crossed together share one slot
@@ -1939,6 +1993,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
             if (saved.literal_snapshots) break;
         }
         start_snapshot_copies(c, before);
+        if (c->snap_hook && (int)c->snaps.size() > before) c->snap_hook(before);
     };
     try {
         c->levels.clear();
@@ -2055,6 +2110,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     } catch (...) {
         c->ref_target = -1.0;
         c->keep_snaps = false;
+        c->keep_cancel = false;
         c->params = saved;
         c->levels = saved_levels;
         c->n_slots = saved_slots;
@@ -2082,6 +2138,7 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
     s.k = inner_total;
     write_state(c, s);
     *c->st_host = s;
+    c->keep_cancel = false;
     reset_solve(c);
     c->keep_snaps = false;
     c->k_host = inner_total;
@@ -2097,6 +2154,23 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
         info->t_total = now_s() - t0;
         info->kkt = K;
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
+                       pdhg_refine_info *info) {
+    API_BEGIN(c)
+    if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
+    pdhg_refine_params R;
+    if (rp)
+        R = *rp;
+    else
+        pdhg_refine_params_default(&R);
+    if (!refine_params_ok(R)) return fail(c, PDHG_E_ARG, "invalid refinement parameters");
+    refine_impl(c, R, info);
     return PDHG_OK;
     API_END(c)
 }

@@ -224,12 +224,7 @@ class Solver:
         L.check(self.lib.pdhg_set_snapshot_callback(self.ctx, self._cb, None), self.ctx)
 
     # ------------------------------------------------------------- Algorithm 1
-    def concurrent_crossover(self, fn, max_threads: int = 0,
-                             max_iters: int = 2 ** 62):
-        """Algorithm 1: fn(idx, info, x, y, z, cancelled) -> bool runs on a
-        library thread for every snapshot (idx -1: the converged iterate);
-        x, y, z are numpy views valid during the call, cancelled() tells
-        whether another call has already won.  Returns (winner, status)."""
+    def _crossover_fn(self, fn):
         n, m = self.n, self.m
 
         def _fn(user, idx, info, px, py, pz, pcancel):
@@ -243,12 +238,35 @@ class Solver:
                 ok = False
             return 1 if ok else 0
 
-        cb = L.CROSSOVER_FN(_fn)
+        return L.CROSSOVER_FN(_fn)
+
+    def concurrent_crossover(self, fn, max_threads: int = 0,
+                             max_iters: int = 2 ** 62):
+        """Algorithm 1: fn(idx, info, x, y, z, cancelled) -> bool runs on a
+        library thread for every snapshot (idx -1: the converged iterate);
+        x, y, z are numpy views valid during the call, cancelled() tells
+        whether another call has already won.  Returns (winner, status)."""
+        cb = self._crossover_fn(fn)
         win, st = C.c_int(0), C.c_int(0)
         L.check(self.lib.pdhg_concurrent_crossover(self.ctx, cb, None, max_threads,
                                                    int(max_iters), C.byref(win),
                                                    C.byref(st)), self.ctx)
         return win.value, st.value
+
+    def concurrent_crossover_refined(self, fn, max_threads: int = 0, **kw):
+        """Algorithm 1 over FP32 bulk iterations with FP64 refinement (keyword
+        arguments as for solve_refined).  Returns (winner, status, info)."""
+        cb = self._crossover_fn(fn)
+        rp = L.RefineParams()
+        L.check(self.lib.pdhg_refine_params_default(C.byref(rp)))
+        for k, v in kw.items():
+            setattr(rp, k, v)
+        info = L.RefineInfo()
+        win, st = C.c_int(0), C.c_int(0)
+        L.check(self.lib.pdhg_concurrent_crossover_refined(
+            self.ctx, cb, None, max_threads, C.byref(rp), C.byref(win),
+            C.byref(st), C.byref(info)), self.ctx)
+        return win.value, st.value, info.asdict()
 
     # ------------------------------------------------------------- refinement
     def solve_refined(self, **kw) -> dict:

@@ -69,3 +69,49 @@ def test_no_winner_runs_final_crossover_on_converged_iterate(Solver, oracle):
     assert winner == -2 and status == 1
     assert sorted(seen)[0] == (-1, 1e-6)
     assert sorted(l for i, l in seen if i >= 0) == [1e-4, 1e-2]
+
+
+def test_refined_harness_launches_from_refined_snapshots(Solver, oracle):
+    # Algorithm 1 over FP32 + refinement: the refined iterate's snapshots
+    # start the crossovers; the first that succeeds stops the refinement
+    lp = lpgen.planted_powerlaw(m=4000, n=20000, kmax=1000, seed=1)
+    levels = oracle.alg1_levels(1e-2, 1e-9)
+    calls, lock = [], threading.Lock()
+
+    def crossover(idx, info, x, y, z, cancelled):
+        with lock:
+            calls.append((idx, info["level"], info["maxresid"]))
+        kk = oracle.kkt(lp, x.copy(), y.copy())
+        assert kk["maxresid"] <= info["level"]
+        if info["level"] > 1e-6:
+            while not cancelled():
+                time.sleep(0.005)
+            return False
+        return True
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-9, levels=levels)
+        winner, status, info = s.concurrent_crossover_refined(crossover)
+        snaps = [s.snapshot(i)[0] for i in range(s.snapshot_count())]
+    assert winner >= 0 and snaps[winner]["level"] <= 1e-6
+    assert status == 4 and info["status"] == 4          # refinement cancelled
+    assert all(c[2] <= c[1] for c in calls)
+    assert min(c[1] for c in calls) >= 1e-9
+
+
+def test_refined_harness_without_winner_runs_final_crossover(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    seen = []
+
+    def crossover(idx, info, x, y, z, cancelled):
+        seen.append((idx, info["level"]))
+        return False
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-8, levels=[1e-2, 1e-4])
+        winner, status, info = s.concurrent_crossover_refined(crossover, max_threads=1)
+        x, y, _ = s.get_iterate()
+    assert winner == -2 and status == 1 and info["status"] == 1
+    assert (-1, 1e-8) in seen
+    assert sorted(l for i, l in seen if i >= 0) == [1e-4, 1e-2]
+    assert oracle.kkt(lp, x, y)["maxresid"] <= 1e-8
