@@ -82,20 +82,23 @@ def test_refined_harness_launches_from_refined_snapshots(Solver, oracle):
         with lock:
             calls.append((idx, info["level"], info["maxresid"]))
         kk = oracle.kkt(lp, x.copy(), y.copy())
-        assert kk["maxresid"] <= info["level"]
-        if info["level"] > 1e-6:
+        ok.append(kk["maxresid"] <= info["level"])
+        if info["level"] > 1e-3:
             while not cancelled():
                 time.sleep(0.005)
             return False
         return True
 
+    ok = []
     with Solver.from_lp(lp) as s:
         s.configure(eps_rel=1e-9, levels=levels)
         winner, status, info = s.concurrent_crossover_refined(crossover)
         snaps = [s.snapshot(i)[0] for i in range(s.snapshot_count())]
-    assert winner >= 0 and snaps[winner]["level"] <= 1e-6
-    assert status == 4 and info["status"] == 4          # refinement cancelled
-    assert all(c[2] <= c[1] for c in calls)
+    assert winner >= 0 and snaps[winner]["level"] <= 1e-3
+    # the winner's cancel stops the refinement at its next check; a round
+    # already under way may still finish it first
+    assert status in (1, 4) and info["status"] == status
+    assert all(ok) and all(c[2] <= c[1] for c in calls)
     assert min(c[1] for c in calls) >= 1e-9
 
 
