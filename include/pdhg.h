@@ -301,7 +301,9 @@ int pdhg_cancel(pdhg_ctx *ctx);
 int pdhg_get_info(pdhg_ctx *ctx, pdhg_info *out);
 
 /* FP64 relative KKT (Section 2) of: which = 0 current iterate, 1 average
- * (valid after at least one iteration since the last restart). */
+ * (valid after at least one iteration since the last restart; for the
+ * Halpern variant T(z) of the last evaluation), 2 the better of the two by
+ * maxresid (a tie goes to the current iterate); out->candidate says which. */
 int pdhg_residuals(pdhg_ctx *ctx, int which, pdhg_kkt *out);
 
 /* Unscaled current iterate: x (n), y (m), z = max(0, c - A^T y) (n).  Any

@@ -1606,10 +1606,18 @@ int pdhg_get_info(pdhg_ctx *c, pdhg_info *o) {
 
 int pdhg_residuals(pdhg_ctx *c, int which, pdhg_kkt *out) {
     API_BEGIN(c)
-    if (!out || which < 0 || which > 1) return fail(c, PDHG_E_ARG, "bad argument");
+    if (!out || which < 0 || which > 2) return fail(c, PDHG_E_ARG, "bad argument");
     if (!c->configured) return fail(c, PDHG_E_STATE, "configure first");
     read_state(c);
-    kkt_of(c, which, out);
+    if (which < 2) {
+        kkt_of(c, which, out);
+    } else {
+        // the better of the two by maxresid (a tie goes to the current)
+        pdhg_kkt k1;
+        kkt_of(c, 0, out);
+        kkt_of(c, 1, &k1);
+        if (k1.maxresid < out->maxresid) *out = k1;
+    }
     return PDHG_OK;
     API_END(c)
 }

@@ -407,3 +407,13 @@ def test_polishing_success_matches_oracle(Solver, oracle):
     kk = oracle.kkt(lp, x, y)
     assert kk["maxresid"] <= 1e-8
     s.close()
+
+
+def test_residuals_of_the_better_candidate(Solver, oracle):
+    lp = lpgen.make("uniform_m500_n1k")
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-12, eval_every=64)
+        s.iterate(100)                     # mid-way between evaluations
+        k0, k1, kb = s.residuals(0), s.residuals(1), s.residuals(2)
+    want = k1 if k1["maxresid"] < k0["maxresid"] else k0
+    assert kb["maxresid"] == want["maxresid"] and kb["candidate"] == want["candidate"]
