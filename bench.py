@@ -191,6 +191,7 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, args.variant)
+        out["cpu_platform"] = cpu_platform(lp)
 
     print(json.dumps(out), flush=True)
 
@@ -295,6 +296,31 @@ def cpu_baseline(lp, iters, variant):
             "kind": "oracle", "host_cpu": model, "host_cpus": os.cpu_count(),
             "sample": f"{r.info['iters']} PDHG iterations of the same LP incl. "
                       f"evaluations at k=0 and every 64, setup excluded, 1 thread"}
+
+
+def cpu_platform(lp, K: int = 8):
+    """The multi-threaded CPU step pair (no restarts or evaluations) on the
+    same LP, iterations/s against the thread count, with its algorithmic
+    bytes per iteration (CSR with 8-byte row pointers; the primal half reads
+    x, c and writes x and 2x - x_old, the dual half reads y, b, writes y)."""
+    import numpy as np
+    from paper_2510_24429_amd.cpu import cpu_steps
+    nnz, m, n = lp.nnz, lp.m, lp.n
+    bytes_iter = (2 * 12 * nnz + 8 * (m + 1) + 8 * (n + 1) + 8 * m + 8 * n
+                  + 32 * n + 24 * m)
+    cap = os.cpu_count() or 1
+    rows = []
+    t = 1
+    while t <= cap:
+        _, _, secs = cpu_steps(lp, np.zeros(n), np.zeros(m), 1e-3, 1e-3, K, t)
+        ips = K / secs
+        rows.append({"threads": t, "iters_s": round(ips, 2),
+                     "GB_s": round(bytes_iter * ips / 1e9, 1)})
+        print(f"[bench] cpu steps, {t} threads: {ips:.1f} iters/s", file=sys.stderr,
+              flush=True)
+        t = t * 2 if t * 2 <= cap or t == cap else cap
+    return {"kind": "cpu step pair", "steps_per_point": K, "bytes_per_iter": bytes_iter,
+            "scaling": rows}
 
 
 if __name__ == "__main__":

@@ -421,6 +421,24 @@ int pdhg_unrolled_backward(pdhg_tape *tape, const double *gxK, double *gc,
  * pdhg_unrolled_backward on them returns PDHG_E_STATE. */
 void pdhg_tape_free(pdhg_tape *tape);
 
+/* ---- the CPU platform (host only) ---------------------------------------- */
+
+/* K plain PDHG steps on the host's cores (the paper's multi-threaded CPU
+ * PDHG, Section 4.1; its bandwidth remark, Section 5): with `threads`
+ * threads, each owning a contiguous range of rows of equal nonzero count,
+ *   x <- max(0, x - tau (c - A^T y))   over the rows of A^T (at_*),
+ *   y <- y + sigma (b - A (2 x_new - x_old))   over the rows of A (a_*),
+ * a barrier between the halves.  The matrices are used as given (pass the
+ * scaled ones for scaled steps); x (n) and y (m) are updated in place;
+ * *seconds (may be NULL) receives the wall time of the K steps.  No GPU is
+ * used.  Returns PDHG_OK, PDHG_E_ARG or PDHG_E_OOM. */
+int pdhg_cpu_steps(int64_t m, int64_t n, const int64_t *a_rp,
+                   const int32_t *a_ci, const double *a_v,
+                   const int64_t *at_rp, const int32_t *at_ci,
+                   const double *at_v, const double *b, const double *c,
+                   double tau, double sigma, int K, int threads, double *x,
+                   double *y, double *seconds);
+
 /* ---- kernels for checking and measurement ------------------------------ */
 
 /* One binned SpMV on the device: which = 0: out (m) = A in (n);

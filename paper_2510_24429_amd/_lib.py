@@ -159,6 +159,8 @@ SIGNATURES = {
     "pdhg_bin_stats": (i32, [vp, i32, vp]),
     "pdhg_panel_count": (i32, [vp, i32, vp]),
     "pdhg_choose_panels": (i32, [i64, i64, i64]),
+    "pdhg_cpu_steps": (i32, [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double,
+                             C.c_double, i32, i32, vp, vp, vp]),
     "pdhg_plan_panels": (i32, [i64, i64, vp, vp, i32, vp, i32, vp, vp, vp, i64]),
     "pdhg_profile": (i32, [vp, i32]),
     "pdhg_kernel_times": (i32, [vp, C.POINTER(KernelTime), i32,
