@@ -94,7 +94,6 @@ struct DevCsr {
     int nsplit64 = 0, nsplit32 = 0, maxparts64 = 1, maxparts32 = 1;
     double *part64 = nullptr;   // split partial sums
     float *part32 = nullptr;
-    double *part64_f32blk = nullptr;  // FP64 sums over the FP32 bins
     int64_t counts64[3] = {0, 0, 0};
     // column panels (P > 1): the stacked panel matrix (P * rows rows, its
     // values kept equal to v64 / v32 through src), and the partial sums
