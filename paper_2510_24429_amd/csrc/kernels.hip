@@ -120,6 +120,24 @@ struct SpmvElem {
 
 // ---------------------------------------------------------------- epilogues
 
+// An epilogue may split into pre(r), the loads of its own operands of row r,
+// and fin(r, s, pre), the update with the row sum s; multi-row blocks then
+// issue the loads at their start, ahead of the row sums (operator() is
+// fin(r, s, pre(r))).  Epilogues without a Pre type run after the sums.
+template <class Epi, class = void>
+struct has_pre : std::false_type {};
+template <class Epi>
+struct has_pre<Epi, std::void_t<typename Epi::Pre>> : std::true_type {};
+struct NoPre {};
+template <class Epi, bool = has_pre<Epi>::value>
+struct PreOf {
+    using type = NoPre;
+};
+template <class Epi>
+struct PreOf<Epi, true> {
+    using type = typename Epi::Pre;
+};
+
 template <typename OutT, typename Acc>
 struct StoreEpi {
     OutT *out;
@@ -155,21 +173,19 @@ struct PrimalEpi {
         t = (T)(double)(st->t_base + off + 1);
         return true;
     }
-    __device__ __forceinline__ void operator()(int j, T g) const {
-        const T v = x[j] - tau * (c[j] - g);
-        T xn = v;
-        if (HAS_L) {
-            const T lj = l[j];
-            xn = v < lj ? lj : v;
-        } else {
-            xn = v < (T)0 ? (T)0 : v;
-        }
-        x[j] = xn;
-        if (AVG) {
-            const T xb = xbar[j];
-            xbar[j] = xb + (xn - xb) / t;
-        }
+    struct Pre {
+        T x, c, l, xb;
+    };
+    __device__ __forceinline__ Pre pre(int j) const {
+        return {x[j], c[j], HAS_L ? l[j] : (T)0, AVG ? xbar[j] : (T)0};
     }
+    __device__ __forceinline__ void fin(int j, T g, const Pre &p) const {
+        const T v = p.x - tau * (p.c - g);
+        const T xn = v < p.l ? p.l : v;
+        x[j] = xn;
+        if (AVG) xbar[j] = p.xb + (xn - p.xb) / t;
+    }
+    __device__ __forceinline__ void operator()(int j, T g) const { fin(j, g, pre(j)); }
 };
 
 // Fused extrapolated dual step over a row i of A~ (q = (A~ x_new)_i):
@@ -188,15 +204,19 @@ struct DualEpi {
         t = (T)(double)(st->t_base + off + 1);
         return true;
     }
-    __device__ __forceinline__ void operator()(int i, T q) const {
-        const T yn = y[i] + sigma * (b[i] - ((q + q) - ax[i]));
+    struct Pre {
+        T y, b, a, yb;
+    };
+    __device__ __forceinline__ Pre pre(int i) const {
+        return {y[i], b[i], ax[i], AVG ? ybar[i] : (T)0};
+    }
+    __device__ __forceinline__ void fin(int i, T q, const Pre &p) const {
+        const T yn = p.y + sigma * (p.b - ((q + q) - p.a));
         y[i] = yn;
         ax[i] = q;
-        if (AVG) {
-            const T yb = ybar[i];
-            ybar[i] = yb + (yn - yb) / t;
-        }
+        if (AVG) ybar[i] = p.yb + (yn - p.yb) / t;
     }
+    __device__ __forceinline__ void operator()(int i, T q) const { fin(i, q, pre(i)); }
 };
 
 // Reflected Halpern step, primal part over a row j of A~^T:
@@ -218,14 +238,19 @@ struct PrimalHalpernEpi {
         rho = (T)st->reflect;
         return true;
     }
-    __device__ __forceinline__ void operator()(int j, T g) const {
-        const T xj = x[j];
-        const T v = xj - tau * (c[j] - g);
-        const T lj = HAS_L ? l[j] : (T)0;
-        const T xhv = v < lj ? lj : v;
-        xh[j] = xhv;
-        x[j] = lam * (((T)1 + rho) * xhv - rho * xj) + ((T)1 - lam) * x0[j];
+    struct Pre {
+        T x, c, l, x0;
+    };
+    __device__ __forceinline__ Pre pre(int j) const {
+        return {x[j], c[j], HAS_L ? l[j] : (T)0, x0[j]};
     }
+    __device__ __forceinline__ void fin(int j, T g, const Pre &p) const {
+        const T v = p.x - tau * (p.c - g);
+        const T xhv = v < p.l ? p.l : v;
+        xh[j] = xhv;
+        x[j] = lam * (((T)1 + rho) * xhv - rho * p.x) + ((T)1 - lam) * p.x0;
+    }
+    __device__ __forceinline__ void operator()(int j, T g) const { fin(j, g, pre(j)); }
 };
 
 // Reflected Halpern step, dual part over a row i of A~ (q = (A~ x^)_i):
@@ -247,12 +272,18 @@ struct DualHalpernEpi {
         rho = (T)st->reflect;
         return true;
     }
-    __device__ __forceinline__ void operator()(int i, T q) const {
-        const T a = ax[i], yi = y[i];
-        const T yhv = yi + sigma * (b[i] - ((q + q) - a));
-        y[i] = lam * (((T)1 + rho) * yhv - rho * yi) + ((T)1 - lam) * y0[i];
-        ax[i] = lam * (((T)1 + rho) * q - rho * a) + ((T)1 - lam) * ax0[i];
+    struct Pre {
+        T a, y, b, y0, a0;
+    };
+    __device__ __forceinline__ Pre pre(int i) const {
+        return {ax[i], y[i], b[i], y0[i], ax0[i]};
     }
+    __device__ __forceinline__ void fin(int i, T q, const Pre &p) const {
+        const T yhv = p.y + sigma * (p.b - ((q + q) - p.a));
+        y[i] = lam * (((T)1 + rho) * yhv - rho * p.y) + ((T)1 - lam) * p.y0;
+        ax[i] = lam * (((T)1 + rho) * q - rho * p.a) + ((T)1 - lam) * p.a0;
+    }
+    __device__ __forceinline__ void operator()(int i, T q) const { fin(i, q, pre(i)); }
 };
 
 // Evaluation of T(z) in FP64 arithmetic (storage T): primal part over a row j
@@ -400,6 +431,10 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
     // (contiguous, <= TILE - 3) into LDS in aligned groups of four per lane
     // (16-byte loads), index and value loads first, then the gathers
     const int R = b.r1 - b.r0;
+    // the epilogue's own operands of this thread's row, loaded first
+    typename PreOf<Epi>::type pre{};
+    if constexpr (has_pre<Epi>::value)
+        if (R <= kWG && tid < R) pre = epi.pre(b.r0 + tid);
     const int p0 = rp[b.r0];
     const int nz = rp[b.r1] - p0;
     for (int r = tid; r <= R; r += kWG) s_rp[r] = rp[b.r0 + r] - p0;
@@ -438,7 +473,12 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
         if (r < R && lane == 0) s_sum[r] = s;
         __syncthreads();
         // epilogue on consecutive rows by consecutive threads
-        if (tid < R) epi(b.r0 + tid, s_sum[tid]);
+        if (tid < R) {
+            if constexpr (has_pre<Epi>::value)
+                epi.fin(b.r0 + tid, s_sum[tid], pre);
+            else
+                epi(b.r0 + tid, s_sum[tid]);
+        }
     } else {
         for (int r = tid; r < R; r += kWG) {
             const int q1 = s_rp[r + 1];
