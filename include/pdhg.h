@@ -460,7 +460,14 @@ int pdhg_spmv(pdhg_ctx *ctx, int which, int scaled, int precision,
  *      deterministic but round differently from P = 1;
  *  "stream_nt": 1 streams the CSR arrays with non-temporal loads, 0 with
  *      plain loads, -1 (default) chooses per side: non-temporal when the
- *      FP64 gather table per XCD (8 cols / P bytes) exceeds 3 MiB.
+ *      FP64 gather table per XCD (8 cols / P bytes) exceeds 3 MiB;
+ *  "sort_rows", "sort_cols": internal order of A's rows / columns: 1 sorts
+ *      them by decreasing length, 0 keeps the given order, -1 (default)
+ *      sorts a dimension only when its longest line exceeds 8 times the
+ *      mean.  Results round differently with another order, and the
+ *      reported iterates stay in the caller's order either way;
+ *  "block_rows": at most this many rows per multi-row block (0, the
+ *      default, leaves the cap at the tile's nonzero count).
  * Returns PDHG_E_ARG for an unknown key or a value out of range. */
 int pdhg_set_tuning(pdhg_ctx *ctx, const char *key, int64_t value);
 /* Row-block statistics of matrix which (0 = A, 1 = A^T): counts of blocks

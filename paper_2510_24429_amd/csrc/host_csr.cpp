@@ -249,14 +249,21 @@ namespace pdhg {
 // into parts of split_chunk nonzeros on several workgroups.  Single-row and
 // split blocks are placed first so that the longest work starts first.
 HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
-                          int64_t split_threshold, int64_t split_chunk) {
+                          int64_t split_threshold, int64_t split_chunk,
+                          int max_rows, bool skip_empty) {
     HostBins hb;
+    // rows per multi-row block: at most `tile`, and at most max_rows if set
+    const int64_t row_cap = max_rows > 0 ? std::min<int64_t>(tile, max_rows) : tile;
     std::vector<RowBlock> longb, multi;
     std::vector<std::pair<int64_t, int64_t>> singles;  // (len, row)
     int slot = 0;
     int64_t r = 0;
     while (r < rows) {
         int64_t len = rp[r + 1] - rp[r];
+        if (skip_empty && len == 0) {   // no block starts at an empty row
+            ++r;
+            continue;
+        }
         if (len > tile) {
             if (len > split_threshold) {
                 int nparts = (int)((len + split_chunk - 1) / split_chunk);
@@ -274,7 +281,7 @@ HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
             continue;
         }
         int64_t r1 = r, acc = 0;
-        while (r1 < rows && (r1 - r) < tile) {
+        while (r1 < rows && (r1 - r) < row_cap) {
             int64_t l = rp[r1 + 1] - rp[r1];
             if (l > tile || acc + l > tile) break;
             acc += l;
@@ -334,7 +341,8 @@ static std::vector<int64_t> even_cuts(int64_t k, int P) {
 
 Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
                   const int32_t *a_ci, const double *a_v,
-                  const int64_t *at_rp, int panels_a, int panels_at) {
+                  const int64_t *at_rp, int panels_a, int panels_at,
+                  int sort_rows, int sort_cols) {
     Relabeled R;
     R.pr.resize((size_t)m);
     R.pc.resize((size_t)n);
@@ -348,8 +356,9 @@ Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
         for (int64_t i = 0; i < k; ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
         return k > 0 && (double)mx > kSkew * (double)rp[k] / (double)k;
     };
-    R.sorted_rows = skewed(a_rp, m);
-    R.sorted_cols = skewed(at_rp, n);
+    // sort_rows / sort_cols: -1 decides by skew, 0 keeps, 1 sorts
+    R.sorted_rows = sort_rows < 0 ? skewed(a_rp, m) : sort_rows == 1;
+    R.sorted_cols = sort_cols < 0 ? skewed(at_rp, n) : sort_cols == 1;
     if (R.sorted_rows)
         std::stable_sort(R.pr.begin(), R.pr.end(), [&](int32_t a, int32_t b) {
             return a_rp[a + 1] - a_rp[a] > a_rp[b + 1] - a_rp[b];
@@ -483,6 +492,10 @@ Panels build_panels(int64_t rows, const int64_t *rp, const int32_t *ci, int P,
             q = q1;
         }
     }
+    S.mask.assign((size_t)rows, 0);
+    for (int p = 0; p < P; ++p)
+        for (int64_t i = 0; i < rows; ++i)
+            if (S.rp[(size_t)p * rows + i + 1] > 0) S.mask[i] |= (uint8_t)(1u << p);
     for (int64_t r = 0; r < (int64_t)P * rows; ++r) S.rp[r + 1] += S.rp[r];
     S.ci.resize((size_t)nnz);
     S.src.resize((size_t)nnz);
@@ -500,14 +513,19 @@ Panels build_panels(int64_t rows, const int64_t *rp, const int32_t *ci, int P,
 // the blocks of panel p are spread over the XCDs x with x % P == p, and the
 // launch order puts XCD x's i-th block at index 8 i + x (empty blocks, r0 ==
 // r1, pad queues of unequal length).  Split slots are renumbered to be global.
+// No block starts at an empty stacked row, so runs of them (a row whose
+// entries all lie in other panels, as in block-structured LPs) cost no
+// blocks; the combine reads only the partials of a row's non-empty panels.
 HostBins build_panel_blocks(int64_t rows, const int64_t *srp, int P, int tile,
-                            int64_t split_threshold, int64_t split_chunk) {
+                            int64_t split_threshold, int64_t split_chunk,
+                            int max_rows) {
     constexpr int kXcd = 8;
     HostBins out;
     std::vector<std::vector<RowBlock>> q(kXcd);
     for (int p = 0; p < P; ++p) {
         HostBins hb = build_row_blocks(rows, srp + (size_t)p * rows, tile,
-                                       split_threshold, split_chunk);
+                                       split_threshold, split_chunk, max_rows,
+                                       true);
         const int32_t roff = (int32_t)((int64_t)p * rows);
         const int slot0 = (int)out.splits.size();
         for (auto sp : hb.splits) {

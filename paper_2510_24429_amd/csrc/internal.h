@@ -46,7 +46,8 @@ struct HostBins {
 };
 
 HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
-                          int64_t split_threshold, int64_t split_chunk);
+                          int64_t split_threshold, int64_t split_chunk,
+                          int max_rows = 0, bool skip_empty = false);
 
 // Column panels of one SpMV side (see host_csr.cpp): the number of panels P
 // (1, 2, 4 or 8) for a matrix of `rows` rows whose gather table has `cols`
@@ -55,11 +56,13 @@ int choose_panels(int64_t rows, int64_t cols, int64_t nnz);
 struct Panels {
     std::vector<int64_t> rp;      // P * rows + 1
     std::vector<int32_t> ci, src;
+    std::vector<uint8_t> mask;    // rows: bit p set when stacked row p*rows+i has entries
 };
 Panels build_panels(int64_t rows, const int64_t *rp, const int32_t *ci, int P,
                     const std::vector<int64_t> &cut);
 HostBins build_panel_blocks(int64_t rows, const int64_t *srp, int P, int tile,
-                            int64_t split_threshold, int64_t split_chunk);
+                            int64_t split_threshold, int64_t split_chunk,
+                            int max_rows = 0);
 
 // The internal (relabeled) problem: row i' of A' is row pr[i'] of A, column
 // j' of A' is column pc[j'] of A; apos[p'] is the position in A's arrays of
@@ -75,7 +78,8 @@ struct Relabeled {
 };
 Relabeled relabel(int64_t m, int64_t n, int64_t nnz, const int64_t *a_rp,
                   const int32_t *a_ci, const double *a_v,
-                  const int64_t *at_rp, int panels_a, int panels_at);
+                  const int64_t *at_rp, int panels_a, int panels_at,
+                  int sort_rows = -1, int sort_cols = -1);
 
 // Matrix resident on the device: CSR with int32 row pointers.
 struct DevCsr {
@@ -101,6 +105,7 @@ struct DevCsr {
     int stream_nt = 0;          // non-temporal streamed loads (see kernels)
     DevCsr *pan = nullptr;
     int32_t *pan_src = nullptr;
+    uint8_t *pan_mask = nullptr;  // per row: which panels hold entries of it
     double *q64 = nullptr;
     float *q32 = nullptr;
 };

@@ -504,16 +504,22 @@ __global__ __launch_bounds__(kFixThreads) void k_split_fix(
     epi(r.row, s);
 }
 
-// Rows of a panelled matrix: the P partial sums of row i (stacked rows
-// p * rows + i) added in panel order, then the epilogue.
+// Rows of a panelled matrix: the partial sums of row i (stacked rows
+// p * rows + i) over the panels that hold entries of it (bits of mask[i];
+// all panels when mask is null), added in panel order, then the epilogue.
+// Partials of empty stacked rows are neither written nor read; skipping
+// them drops only exact zeros.
 template <typename Acc, class Epi>
 __global__ __launch_bounds__(kWG) void k_panel_combine(
-    const Acc *__restrict__ q, int P, int rows, Epi epi_in) {
+    const Acc *__restrict__ q, const uint8_t *__restrict__ mask, int P,
+    int rows, Epi epi_in) {
     Epi epi = epi_in;
     if (!epi.begin()) return;
     for (int i = blockIdx.x * kWG + threadIdx.x; i < rows; i += gridDim.x * kWG) {
-        Acc s = q[i];
-        for (int p = 1; p < P; ++p) s += q[(int64_t)p * rows + i];
+        const unsigned m = mask ? mask[i] : 0xffu;
+        Acc s = (Acc)0;
+        for (int p = 0; p < P; ++p)
+            if (m & (1u << p)) s += q[(int64_t)p * rows + i];
         epi(i, s);
     }
 }
@@ -587,7 +593,7 @@ void rb_spmv(const DevCsr &M, const MT *vals, const VT *in, Epi e,
                       PanelEpi<Epi, Acc>{e, q}, s);
     hipLaunchKernelGGL((k_panel_combine<Acc, Epi>),
                        dim3(grid_for(M.rows, kWG, 4096)), dim3(kWG), 0, s, q,
-                       M.P, (int)M.rows, e);
+                       M.pan_mask, M.P, (int)M.rows, e);
 }
 
 }  // namespace

@@ -7,6 +7,7 @@
 // writes (status, snapshot levels fired, restart counters).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -102,6 +103,8 @@ struct pdhg_ctx {
     int64_t split_chunk = (int64_t)1 << 16;
     int panels_a = 0, panels_at = 0;    // column panels per side; 0 = choose
     int stream_nt = -1;                 // streamed-load kind; -1 = choose
+    int sort_rows = -1, sort_cols = -1; // length sort of rows / columns; -1 = by skew
+    int block_rows = 0;                 // row cap of multi-row blocks; 0 = tile
 
     // scaling and scaled data
     double *dr = nullptr, *dc = nullptr;
@@ -281,6 +284,7 @@ void free_csr(DevCsr &M) {
         delete M.pan;
     }
     dfree(M.pan_src);
+    dfree(M.pan_mask);
     dfree(M.q64);
     dfree(M.q32);
     dfree(M.rp);
@@ -423,8 +427,14 @@ void upload_panels(pdhg_ctx *c, DevCsr &M, const std::vector<int64_t> &rp,
         HIPC(hipMemcpy(T.ci, S.ci.data(), M.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPC(hipMemcpy(M.pan_src, S.src.data(), M.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    upload_bins(T, build_panel_blocks(M.rows, S.rp.data(), P, kTile64 - 3, c->split_threshold, c->split_chunk),
-                build_panel_blocks(M.rows, S.rp.data(), P, kTile32 - 3, c->split_threshold, c->split_chunk));
+    upload_bins(T, build_panel_blocks(M.rows, S.rp.data(), P, kTile64 - 3, c->split_threshold, c->split_chunk, c->block_rows),
+                build_panel_blocks(M.rows, S.rp.data(), P, kTile32 - 3, c->split_threshold, c->split_chunk, c->block_rows));
+    // the mask is needed only when some row misses some panel
+    const uint8_t full = (uint8_t)((1u << P) - 1);
+    if (std::any_of(S.mask.begin(), S.mask.end(), [&](uint8_t k) { return k != full; })) {
+        M.pan_mask = dmalloc<uint8_t>(M.rows);
+        HIPC(hipMemcpy(M.pan_mask, S.mask.data(), M.rows * sizeof(uint8_t), hipMemcpyHostToDevice));
+    }
     M.q64 = dmalloc<double>(T.rows);
     M.q32 = dmalloc<float>(T.rows);
 }
@@ -457,8 +467,8 @@ void upload_csr(pdhg_ctx *c, DevCsr &M, int64_t rows, int64_t cols,
     }
     // multi-row blocks hold at most TILE - 3 nonzeros: an aligned window of
     // TILE entries then always covers them
-    upload_bins(M, build_row_blocks(rows, rp.data(), kTile64 - 3, c->split_threshold, c->split_chunk),
-                build_row_blocks(rows, rp.data(), kTile32 - 3, c->split_threshold, c->split_chunk));
+    upload_bins(M, build_row_blocks(rows, rp.data(), kTile64 - 3, c->split_threshold, c->split_chunk, c->block_rows),
+                build_row_blocks(rows, rp.data(), kTile32 - 3, c->split_threshold, c->split_chunk, c->block_rows));
     if (P > 1) upload_panels(c, M, rp, ci, P, cut);
     // stream the CSR non-temporally when the FP64 gather table each XCD
     // works on exceeds 3 MiB, so that streaming does not evict it from L2
@@ -1148,6 +1158,18 @@ int pdhg_set_tuning(pdhg_ctx *c, const char *key, int64_t value) {
         c->stream_nt = (int)value;
         return PDHG_OK;
     }
+    if (std::strcmp(key, "block_rows") == 0 && value >= 0 && value <= (1 << 20)) {
+        c->block_rows = (int)value;
+        return PDHG_OK;
+    }
+    if (std::strcmp(key, "sort_rows") == 0 && value >= -1 && value <= 1) {
+        c->sort_rows = (int)value;
+        return PDHG_OK;
+    }
+    if (std::strcmp(key, "sort_cols") == 0 && value >= -1 && value <= 1) {
+        c->sort_cols = (int)value;
+        return PDHG_OK;
+    }
     return fail(c, PDHG_E_ARG, "unknown tuning key or value out of range");
 }
 
@@ -1184,7 +1206,7 @@ int pdhg_load(pdhg_ctx *c, int64_t m, int64_t n, int64_t nnz,
     const int pa = c->panels_a ? c->panels_a : choose_panels(m, n, nnz);
     const int pat = c->panels_at ? c->panels_at : choose_panels(n, m, nnz);
     Relabeled R = relabel(m, n, nnz, h_arp.data(), h_aci.data(), h_av.data(),
-                          h_atrp.data(), pa, pat);
+                          h_atrp.data(), pa, pat, c->sort_rows, c->sort_cols);
     std::vector<int32_t>().swap(h_aci);
     std::vector<double>().swap(h_av);
     upload_csr(c, c->A, m, n, nnz, R.a_rp, R.a_ci, R.a_v, pa, R.a_cut);

@@ -232,8 +232,9 @@ def test_column_panels_partition_every_row(P):
             s0, s1 = srp[p * rows + i], srp[p * rows + i + 1]
             want = cols_i[(cols_i >= cut[p]) & (cols_i < cut[p + 1])]
             assert np.array_equal(lp.a_ci[src[s0:s1]], want)
-    # blocks: every stacked row exactly once, a block never leaves its panel,
-    # and the block at launch index w serves panel (w % 8) % P
+    # blocks: every non-empty stacked row exactly once (empty ones at most
+    # once: no block starts at one), a block never leaves its panel, and the
+    # block at launch index w serves panel (w % 8) % P
     covered = np.zeros(P * rows, dtype=np.int64)
     for w, (r0, r1, part, nparts) in enumerate(blk):
         if r0 == r1:
@@ -242,11 +243,35 @@ def test_column_panels_partition_every_row(P):
         assert (r1 - 1) // rows == p and (w % 8) % P == p
         assert nparts == 1
         covered[r0:r1] += 1
+        assert srp[r0 + 1] > srp[r0]
         if r1 - r0 > 1:
             assert srp[r1] - srp[r0] <= 1021
-    assert np.all(covered == 1)
+    nonempty = np.diff(srp) > 0
+    assert np.all(covered[nonempty] == 1) and np.all(covered[~nonempty] <= 1)
     # XCD queues hold whole rows of the 8-wide launch grid
     assert len(blk) % 8 == 0
+
+
+def test_column_panels_skip_empty_runs():
+    # block-diagonal rows: each row's entries lie in one panel, so 3 of its 4
+    # stacked rows are empty; blocks must cover the non-empty ones once and
+    # leave the long empty runs alone
+    rng = np.random.default_rng(7)
+    rows, cols, P = 4000, 4000, 4
+    rp = np.arange(rows + 1, dtype=np.int64) * 5
+    ci = np.concatenate([np.sort(rng.choice(1000, 5, replace=False)) + 1000 * (i // 1000)
+                         for i in range(rows)]).astype(np.int32)
+    cut = np.array([0, 1000, 2000, 3000, 4000], dtype=np.int64)
+    srp, src, blk = _plan_panels(rp, ci, cols, P, cut)
+    nonempty = np.diff(srp) > 0
+    assert nonempty.sum() == rows
+    covered = np.zeros(P * rows, dtype=np.int64)
+    for r0, r1, part, nparts in blk:
+        covered[r0:r1] += 1
+    assert np.all(covered[nonempty] == 1)
+    # each panel's run of non-empty rows ends in at most one block that
+    # reaches into the following empty run
+    assert covered.sum() <= rows + P * 1021
 
 
 def test_panel_choice_follows_table_size():
