@@ -199,7 +199,8 @@ def main():
 def _kernel_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
+    # the kernels, their launch shapes and the row-block planner
+    for f in ("kernels.hip", "internal.h", "host_csr.cpp"):
         with open(os.path.join(ROOT, "paper_2510_24429_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -466,8 +466,9 @@ int pdhg_spmv(pdhg_ctx *ctx, int which, int scaled, int precision,
  *      sorts a dimension only when its longest line exceeds 8 times the
  *      mean.  Results round differently with another order, and the
  *      reported iterates stay in the caller's order either way;
- *  "block_rows": at most this many rows per multi-row block (0, the
- *      default, leaves the cap at the tile's nonzero count).
+ *  "block_rows": at most this many rows per multi-row block (default 256,
+ *      one per lane of a workgroup; 0 leaves the cap at the tile's nonzero
+ *      count).
  * Returns PDHG_E_ARG for an unknown key or a value out of range. */
 int pdhg_set_tuning(pdhg_ctx *ctx, const char *key, int64_t value);
 /* Row-block statistics of matrix which (0 = A, 1 = A^T): counts of blocks

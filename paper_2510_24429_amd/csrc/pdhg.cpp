@@ -104,7 +104,7 @@ struct pdhg_ctx {
     int panels_a = 0, panels_at = 0;    // column panels per side; 0 = choose
     int stream_nt = -1;                 // streamed-load kind; -1 = choose
     int sort_rows = -1, sort_cols = -1; // length sort of rows / columns; -1 = by skew
-    int block_rows = 0;                 // row cap of multi-row blocks; 0 = tile
+    int block_rows = kWG;               // row cap of multi-row blocks; 0 = tile
 
     // scaling and scaled data
     double *dr = nullptr, *dc = nullptr;
