@@ -458,7 +458,7 @@ int choose_panels(int64_t rows, int64_t cols, int64_t nnz) {
     constexpr double kLaunch = 4e-6;      // the extra launch, seconds
     const double table = 8.0 * (double)cols;
     const double whole = (double)nnz / gather_rate(table);
-    double best = 0.9 * whole;            // a split must win clearly
+    double best = 0.95 * whole;           // a split must win clearly
     int bestP = 1;
     for (int P = 2; P <= 8; P *= 2) {
         const double t = (double)nnz / gather_rate(table / P) +

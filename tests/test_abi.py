@@ -282,7 +282,7 @@ def test_panel_choice_follows_table_size():
     assert L.lib().pdhg_choose_panels(200_000, 1_000_000, 9_400_000) > 1
     assert L.lib().pdhg_choose_panels(1_350_000, 4_950_000, 14_550_000) == 8
     assert L.lib().pdhg_choose_panels(5_000_000, 20_000_000, 110_000_000) == 8
-    assert L.lib().pdhg_choose_panels(20_000_000, 5_000_000, 110_000_000) == 1
+    assert L.lib().pdhg_choose_panels(20_000_000, 5_000_000, 110_000_000) == 4
     # ~3 entries per row: splitting the 10.8 MB table costs more than it saves
     assert L.lib().pdhg_choose_panels(4_950_000, 1_350_000, 14_550_000) == 1
     assert L.lib().pdhg_choose_panels(100, 100, 0) == 1
