@@ -161,6 +161,35 @@ def test_iterates_match_multi_tile_ragged(Solver, oracle, variant, panels):
     assert worst <= 1e-10, worst
 
 
+LAYOUTS = [{"block_rows": 0}, {"block_rows": 64},
+           {"sort_rows": 0, "sort_cols": 0},
+           {"sort_rows": 1, "sort_cols": 1, "panels_a": 4, "panels_at": 2}]
+
+
+@pytest.mark.parametrize("tuning", LAYOUTS, ids=["rows_tile", "rows_64", "unsorted", "sorted_panels"])
+def test_iterates_match_with_layout_keys(Solver, oracle, tuning):
+    # the internal order and the row-block shapes change only rounding
+    lp = lpgen.planted_powerlaw(m=3000, n=20000, kmax=2500, seed=21)
+    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, eval_every=32,
+                          variant=1, tuning=tuning)
+    assert worst <= 1e-10, worst
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_iterates_match_block_structured_panels(Solver, oracle, variant):
+    # commodity-major columns cut into 8 panels: a conservation row's entries
+    # lie in one or two panels, so most stacked rows are empty and skipped
+    lp = lpgen.multicommodity(nodes=1500, arcs=6000, commodities=8, seed=5)
+    with Solver.from_lp(lp, tuning={"panels_a": 8, "panels_at": 4}) as s:
+        assert s.panel_count(0) == 8 and s.panel_count(1) == 4
+    # the iteration limit lies past the traced window; it only ends the
+    # oracle's run early
+    worst = _trace_parity(Solver, oracle, lp, 100, eps_rel=1e-8, eval_every=32,
+                          max_iters=101, variant=variant,
+                          tuning={"panels_a": 8, "panels_at": 4})
+    assert worst <= 1e-10, worst
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_panelled_fp32_and_fp64_steps_match_plain(Solver, precision):
     # the panel path changes only the summation order of each row: iterates
