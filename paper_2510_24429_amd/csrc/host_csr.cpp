@@ -307,6 +307,11 @@ HostBins build_row_blocks(int64_t rows, const int64_t *rp, int tile,
         hb.counts[1] += 1;
     }
     for (auto &b : multi) hb.blocks.push_back(b);
+    // nonzero range of each block, so that its loads need no row pointer
+    for (auto &b : hb.blocks) {
+        b.p0 = (int32_t)rp[b.r0];
+        b.p1 = (int32_t)rp[b.r1];
+    }
     return hb;
 }
 

@@ -30,8 +30,11 @@ constexpr int kRedBlocks = 512;   // blocks per side of the KKT reduction
 //    reduce across the workgroup;
 //  - one row split over nparts workgroups: part `part` writes a partial sum
 //    to slot `slot`; a fix-up pass adds the parts in order.
+// A workgroup's rows [r0, r1) and their nonzeros [p0, p1) (the whole row
+// for a split row, whose part `part` of `nparts` the workgroup sums into
+// partial slot `slot`); r0 == r1 marks an empty padding block.
 struct RowBlock {
-    int32_t r0, r1, part, nparts, slot, pad0, pad1, pad2;
+    int32_t r0, r1, part, nparts, slot, p0, p1, pad;
 };
 
 struct SplitRow {

@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
         // one row: the workgroup strides it in aligned groups of four
         // nonzeros per lane (16-byte index and value loads), two groups in
         // flight; entries outside [p0, p1) are masked and never gathered
-        int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
+        int p0 = b.p0, p1 = b.p1;
         if (b.nparts > 1) {
             const int chunk = (p1 - p0 + b.nparts - 1) / b.nparts;
             p0 = p0 + b.part * chunk;
@@ -435,8 +435,8 @@ __global__ __launch_bounds__(kWG) void k_rowblock(
     typename PreOf<Epi>::type pre{};
     if constexpr (has_pre<Epi>::value)
         if (R <= kWG && tid < R) pre = epi.pre(b.r0 + tid);
-    const int p0 = rp[b.r0];
-    const int nz = rp[b.r1] - p0;
+    const int p0 = b.p0;
+    const int nz = b.p1 - p0;
     for (int r = tid; r <= R; r += kWG) s_rp[r] = rp[b.r0 + r] - p0;
     {
         const int a0 = p0 & ~3;
