@@ -215,7 +215,9 @@ int pdhg_check_transpose(int64_t m, int64_t n, int64_t nnz,
  * (first row, end row, part, number of parts) in launch order and returns
  * the number of descriptors (or a negative error).  Rows longer than
  * split_threshold are split into parts of split_chunk nonzeros.  Host only;
- * the library calls the same planner at load time. */
+ * the library calls the same planner at load time, where it also caps a
+ * multi-row block at 256 rows (tuning key "block_rows"); this entry point
+ * applies the tile cap alone. */
 int pdhg_plan_bins(int64_t rows, const int64_t *rp, int tile,
                    int64_t split_threshold, int64_t split_chunk,
                    int32_t *out, int64_t cap);
