@@ -71,7 +71,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not "
               "supported (the multi-GPU sharding is a design note only)",
               file=sys.stderr)
         sys.exit(2)
