@@ -140,7 +140,7 @@ static double nrm2(const double *a, int64_t k) { return sqrt(dot(a, a, k)); }
 /* ------------------------------------------------------ Ruiz scaling ---- */
 
 /*
- * Ruiz l_inf equilibration (the "diagonally preconditioned" part of the
+ * Ruiz l_inf equilibration (the diagonal preconditioning of the
  * method; the paper itself gives no scaling rule).  Every pass takes, from the
  * current scaled matrix (D_r,i * A_ij) * D_c,j, the row maxima rho_i and the
  * column maxima kappa_j at the same time, replaces a zero maximum by 1, and
