@@ -28,6 +28,24 @@ sys.path.insert(0, ROOT)
 METRIC = ("PDHG iters/s + HBM GB/s; time to rel KKT 1e-8, FP32+refine vs "
           "FP64, 1 GPU")
 HBM_PEAK_GBS = 8000.0
+# Random 8-byte gathers per second on the MI355X by the size of the table each
+# XCD gathers from, measured by a probe of gathers alone (<= 2 MB ... >= 128 MB).
+GATHER_MB = (2, 4, 8, 16, 32, 128)
+GATHER_RATE = (195e9, 180e9, 110e9, 77e9, 63e9, 54e9)
+
+
+def gather_ceiling(table_bytes: float) -> float:
+    """Measured random-gather rate for a table of this size (log-log
+    interpolation between the probe's sizes)."""
+    import math
+    x = table_bytes / 1048576.0
+    if x <= GATHER_MB[0]:
+        return GATHER_RATE[0]
+    for i in range(1, len(GATHER_MB)):
+        if x <= GATHER_MB[i]:
+            f = math.log(x / GATHER_MB[i - 1]) / math.log(GATHER_MB[i] / GATHER_MB[i - 1])
+            return GATHER_RATE[i - 1] * (GATHER_RATE[i] / GATHER_RATE[i - 1]) ** f
+    return GATHER_RATE[-1]
 
 
 def alg_bytes(m: int, n: int, nnz: int, fp: int = 8, has_l: bool = False):
@@ -139,6 +157,17 @@ def main():
     iter_gbs = (bp + bd) / ((tp + td) * 1e-3) / 1e9
     print(f"[bench] primal {tp*1e3:.1f}us {gbs_p:.0f}GB/s  dual {td*1e3:.1f}us "
           f"{gbs_d:.0f}GB/s  iteration {iter_gbs:.0f}GB/s", file=sys.stderr, flush=True)
+    # the same kernel against the measured random-gather rate for its table
+    # (y of m entries for the primal step, x of n for the dual step, each
+    # XCD holding 1/P of it when the side is panelled)
+    if dominant == "primal_step":
+        table = 8.0 * lp.m / s.panel_count(1)
+        t_dom = tp
+    else:
+        table = 8.0 * lp.n / s.panel_count(0)
+        t_dom = td
+    g_ach = lp.nnz / (t_dom * 1e-3)
+    g_cap = gather_ceiling(table)
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}.txt")
     if os.path.exists(tfile):
@@ -180,6 +209,10 @@ def main():
                     "iteration_GB_s": round(iter_gbs, 1),
                     "steps_only_iters_s": round(1e3 / (tp + td), 1),
                     "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)},
+        "gather_rate": {"kernel": dominant, "achieved": round(g_ach / 1e9, 1),
+                        "ceiling": round(g_cap / 1e9, 1), "unit": "G gathers/s",
+                        "table_MB": round(table / 1048576.0, 2),
+                        "frac": round(g_ach / g_cap, 4)},
         "restarts_of_run": restarts_of_run,
     }
 
