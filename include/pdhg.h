@@ -489,7 +489,8 @@ int pdhg_choose_panels(int64_t rows, int64_t cols, int64_t nnz);
  * tile `tile` (no splits) are written to out as (r0, r1, part, nparts), up
  * to cap blocks, in launch order: block w runs on XCD w % 8, which serves
  * panel (w % 8) % P; r0 == r1 marks padding.  Returns the number of blocks,
- * or a negative error code. */
+ * or a negative error code (PDHG_E_ARG also when P * rows >= 2^31: stacked
+ * rows are indexed in int32, and pdhg_load halves P until they fit). */
 int pdhg_plan_panels(int64_t rows, int64_t cols, const int64_t *rp,
                      const int32_t *ci, int P, const int64_t *cut, int tile,
                      int64_t *srp, int32_t *src, int32_t *out, int64_t cap);

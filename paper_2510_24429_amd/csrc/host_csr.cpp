@@ -218,7 +218,8 @@ extern "C" int pdhg_plan_panels(int64_t rows, int64_t cols, const int64_t *rp,
                                 int tile, int64_t *srp, int32_t *src,
                                 int32_t *out, int64_t cap) {
     if (rows < 1 || cols < 1 || !rp || !cut || tile < 1 ||
-        !(P == 1 || P == 2 || P == 4 || P == 8) || !srp || !src)
+        !(P == 1 || P == 2 || P == 4 || P == 8) || !srp || !src ||
+        (int64_t)P * rows >= ((int64_t)1 << 31))
         return PDHG_E_ARG;
     if (rp[rows] > 0 && !ci) return PDHG_E_ARG;
     if (cut[0] != 0 || cut[P] != cols) return PDHG_E_ARG;

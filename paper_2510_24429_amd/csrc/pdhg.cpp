@@ -1203,8 +1203,11 @@ int pdhg_load(pdhg_ctx *c, int64_t m, int64_t n, int64_t nnz,
     c->nnz = nnz;
     // column panels: the dual step gathers x (n entries) over A's rows, the
     // primal step y (m entries) over A^T's rows
-    const int pa = c->panels_a ? c->panels_a : choose_panels(m, n, nnz);
-    const int pat = c->panels_at ? c->panels_at : choose_panels(n, m, nnz);
+    int pa = c->panels_a ? c->panels_a : choose_panels(m, n, nnz);
+    int pat = c->panels_at ? c->panels_at : choose_panels(n, m, nnz);
+    // stacked panel rows are indexed in int32: keep P * rows below 2^31
+    while (pa > 1 && (int64_t)pa * m >= ((int64_t)1 << 31)) pa /= 2;
+    while (pat > 1 && (int64_t)pat * n >= ((int64_t)1 << 31)) pat /= 2;
     Relabeled R = relabel(m, n, nnz, h_arp.data(), h_aci.data(), h_av.data(),
                           h_atrp.data(), pa, pat, c->sort_rows, c->sort_cols);
     std::vector<int32_t>().swap(h_aci);

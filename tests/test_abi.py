@@ -252,6 +252,20 @@ def test_column_panels_partition_every_row(P):
     assert len(blk) % 8 == 0
 
 
+def test_column_panels_reject_int32_overflow():
+    # P * rows stacked rows must stay below 2^31; only sizes are read before
+    # the check, so tiny arrays stand in for a matrix of 2^29 rows
+    rp = np.zeros(2, dtype=np.int64)
+    ci = np.zeros(1, dtype=np.int32)
+    cut = np.array([0, 1, 2, 3, 4, 5, 6, 7, 8], dtype=np.int64)
+    srp = np.zeros(2, dtype=np.int64)
+    src = np.zeros(1, dtype=np.int32)
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    rc = L.lib().pdhg_plan_panels(1 << 28, 8, vp(rp), vp(ci), 8, vp(cut), 1021,
+                                  vp(srp), vp(src), None, 0)
+    assert rc == -1
+
+
 def test_column_panels_skip_empty_runs():
     # block-diagonal rows: each row's entries lie in one panel, so 3 of its 4
     # stacked rows are empty; blocks must cover the non-empty ones once and
