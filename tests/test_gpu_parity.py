@@ -379,6 +379,32 @@ def test_full_size_multicommodity_parity(Solver, oracle):
                            equal_nan=True)
 
 
+def test_full_size_coupled_parity(Solver, oracle):
+    """The largest workload at full size (m=5M, n=20M, nnz=110M) in its
+    launch configuration (8 column panels for the dual step, 4 for the
+    primal step, non-temporal streaming): Ruiz factors bitwise, and the first
+    iterations plus evaluations against the oracle."""
+    lp = lpgen.make("coupled_m5m_n20m")
+    dr, dc, _ = oracle.ruiz(lp, 10)
+    K = 3
+    kw = dict(eps_rel=1e-8, eval_every=2, eta=0.5, omega0=1.3, variant=1)
+    ref = oracle.solve(lp, trace_k=K, max_iters=K, **kw)
+    with Solver.from_lp(lp) as s:
+        assert (s.panel_count(0), s.panel_count(1)) == (8, 4)
+        s.configure(**kw)
+        gdr, gdc = s.get_scaling()
+        assert np.array_equal(gdr, dr) and np.array_equal(gdc, dc)
+        for k in range(K):
+            s.iterate(1)
+            x, y, _ = s.get_iterate()
+            assert rel(x, ref.trace_x[k]) <= 1e-10, k
+            assert rel(y, ref.trace_y[k]) <= 1e-10, k
+        log = s.eval_log()
+        assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
+        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0,
+                           equal_nan=True)
+
+
 def test_full_size_powerlaw_parity(Solver, oracle):
     """The benchmark workload at full size (m=200k, n=1M, nnz~9.4M): Ruiz
     factors bitwise, and the first iterations plus one evaluation with a
