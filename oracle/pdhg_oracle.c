@@ -15,8 +15,7 @@
  *     (Section 2, the displayed primal/dual problems and residual vectors);
  *   - optimality: zero residuals, x, z >= 0, zero gap (Section 2);
  *   - the three relative stopping inequalities on ||r_P||_2, ||r_D||_2 and the
- *     objective gap (Section 2, the three inequalities after "Iterations proceed
- *     until all three achieve target tolerances");
+ *     objective gap (Section 2, the three relative stopping inequalities);
  *   - the snapshot schedule of Algorithm 1 (Section 3.1): a snapshot fires when
  *     maxresid <= eps_target, then eps_target shrinks tenfold, until eps_rel.
  * Everything inside the PDHG iteration is not stated in the paper (Section 4.1
