@@ -234,10 +234,12 @@ const char *pdhg_last_error(const pdhg_ctx *ctx);
 
 /* ---- problem data ------------------------------------------------------ */
 
-/* Load CSR A (m x n) and its explicit transpose CSR A^T (n x m), b (m),
- * c (n) and optional lower bounds lb (n; NULL = 0).  Validates both CSRs and
- * the transpose relation (PDHG_E_CSR / PDHG_E_TRANSPOSE), then builds the
- * row-length bins of both matrices.  Replaces any earlier problem. */
+/* Load the data of Section 2's primal problem min c^T x, Ax = b, x >= 0
+ * (with x >= lb when lb is given): CSR A (m x n) and its explicit transpose
+ * CSR A^T (n x m), b (m), c (n) and optional lower bounds lb (n; NULL = 0).
+ * Validates both CSRs and the transpose relation (PDHG_E_CSR /
+ * PDHG_E_TRANSPOSE), then builds the row-length bins of both matrices.
+ * Replaces any earlier problem (and invalidates its adjoint tapes). */
 int pdhg_load(pdhg_ctx *ctx, int64_t m, int64_t n, int64_t nnz,
               const int64_t *a_rp, const int32_t *a_ci, const double *a_v,
               const int64_t *at_rp, const int32_t *at_ci, const double *at_v,
@@ -261,7 +263,9 @@ int pdhg_set_rhs_obj(pdhg_ctx *ctx, const double *b, const double *c, int mem);
 int pdhg_configure(pdhg_ctx *ctx, const pdhg_params *p);
 
 /* Warm start from unscaled x (n) and y (m) (either may be NULL = zero);
- * resets the averages, the restart state and the status. */
+ * resets the averages, the restart state and the status.  The paper's
+ * Algorithm 1 starts PDHG from a given iterate (its input); this sets it.
+ * With no call the iteration starts from zero. */
 int pdhg_set_iterate(pdhg_ctx *ctx, const double *x, const double *y, int mem);
 
 /* Run up to max_iters more iterations (the parameter max_iters bounds the
@@ -296,20 +300,27 @@ int pdhg_set_iterate(pdhg_ctx *ctx, const double *x, const double *y, int mem);
 int pdhg_iterate(pdhg_ctx *ctx, int64_t max_iters, int *status);
 
 /* Ask a running pdhg_iterate / pdhg_solve_refined to stop at its next
- * evaluation check with PDHG_CANCELLED.  Thread-safe and idempotent. */
+ * evaluation check with PDHG_CANCELLED.  Thread-safe and idempotent.  This is
+ * Algorithm 1's termination of the PDHG run once a crossover thread has found
+ * the optimal basis first (Section 3.1); the concurrent-crossover calls below
+ * use it for that, and a caller running its own crossover threads may too. */
 int pdhg_cancel(pdhg_ctx *ctx);
 
 /* Counters, step sizes and the KKT of the current iterate. */
 int pdhg_get_info(pdhg_ctx *ctx, pdhg_info *out);
 
-/* FP64 relative KKT (Section 2) of: which = 0 current iterate, 1 average
+/* FP64 relative KKT errors (Section 2's three relative quantities on the
+ * unscaled problem, and their maximum, Algorithm 1's maxresid) of: which =
+ * 0 current iterate, 1 average
  * (valid after at least one iteration since the last restart; for the
  * Halpern variant T(z) of the last evaluation), 2 the better of the two by
  * maxresid (a tie goes to the current iterate); out->candidate says which. */
 int pdhg_residuals(pdhg_ctx *ctx, int which, pdhg_kkt *out);
 
-/* Unscaled current iterate: x (n), y (m), z = max(0, c - A^T y) (n).  Any
- * pointer may be NULL. */
+/* Unscaled current iterate: the primal x (n) and dual y (m) of Section 2's
+ * pair, and the dual slack z = max(0, c - A^T y) (n), which the paper leaves
+ * implicit for a PDHG iterate; with it, r_D = A^T y + z - c.  Any pointer
+ * may be NULL. */
 int pdhg_get_iterate(pdhg_ctx *ctx, double *x, double *y, double *z, int mem);
 
 /* Ruiz factors of the last configure: dr (m), dc (n). */
@@ -322,17 +333,30 @@ int pdhg_eval_log(pdhg_ctx *ctx, double *out, int cap, int *count);
 
 /* ---- snapshots (Algorithm 1's crossover starting points) --------------- */
 
+/* Number of snapshots emitted since the last configure (or refinement). */
 int pdhg_snapshot_count(pdhg_ctx *ctx, int *count);
 /* Copy snapshot idx (0-based, in emission order): info plus unscaled
- * x (n), y (m), z (n); any pointer may be NULL. */
+ * x (n), y (m), z (n); any pointer may be NULL.  A snapshot is an iterate
+ * Algorithm 1 (Section 3.1) hands to a crossover thread, taken when the
+ * better candidate's maxresid first reaches a level; its z = max(0, c -
+ * A^T y) is the dual slack of Section 2's dual problem. */
 int pdhg_snapshot(pdhg_ctx *ctx, int idx, pdhg_snapshot_info *info,
                   double *x, double *y, double *z, int mem);
-/* Register cb, called on a library thread once a snapshot's host copy is
- * complete, with the snapshot index; cb must not call into the context. */
-int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
-                               void (*cb)(void *user, int idx,
-                                          const pdhg_snapshot_info *info),
-                               void *user);
+/* Snapshot notification: Algorithm 1's hand-over of an iterate to a CPU
+ * crossover thread (Section 3.1; the paper pulls the iterate from the GPU to
+ * the CPU for this).  Called on one library thread, in emission order, once
+ * the snapshot's copy to pinned host memory is complete, with the snapshot
+ * index, its info and its unscaled x (n), y (m), z (n) in that host copy.
+ * The pointers are valid only during the call (copy what is kept); a later
+ * emission of the same level waits until the call has returned.  cb must not
+ * call into the context. */
+typedef void (*pdhg_snapshot_cb)(void *user, int idx,
+                                 const pdhg_snapshot_info *info,
+                                 const double *x, const double *y,
+                                 const double *z);
+/* Register cb (NULL: none) for the snapshots of later iterate / refinement
+ * calls on this context. */
+int pdhg_set_snapshot_callback(pdhg_ctx *ctx, pdhg_snapshot_cb cb, void *user);
 
 /* ---- Algorithm 1: concurrent crossover ---------------------------------- */
 
@@ -340,9 +364,10 @@ int pdhg_set_snapshot_callback(pdhg_ctx *ctx,
  * this library does not implement).  Called on a library thread with a
  * snapshot's unscaled x (n), y (m), z (n) (valid for the duration of the
  * call) and `cancel`, which becomes nonzero once another thread has won; the
- * routine should poll it and return promptly.  Returns 1 if it found a basic
- * optimal solution, 0 otherwise.  idx is the snapshot index, or -1 for the
- * final iterate. */
+ * library writes it with an atomic store, and the routine should poll it
+ * (a volatile or atomic 32-bit load) and return promptly.  Returns 1 if it
+ * found a basic optimal solution, 0 otherwise.  idx is the snapshot index, or
+ * -1 for the final iterate. */
 typedef int (*pdhg_crossover_fn)(void *user, int idx,
                                  const pdhg_snapshot_info *info,
                                  const double *x, const double *y,
@@ -352,8 +377,10 @@ typedef int (*pdhg_crossover_fn)(void *user, int idx,
 /* Concurrent crossover PDHG (Algorithm 1, Section 3.1): iterate; every
  * snapshot the configured levels emit (for the paper's schedule, configure
  * with pdhg_alg1_levels(eps_cross, eps_rel)) launches `fn` on a new host
- * thread, at most max_threads at a time (a later snapshot waits for a free
- * thread; 0 means no limit).  The first call to return 1 wins: the others see
+ * thread, at most max_threads at a time (0 means no limit).  A snapshot that
+ * finds every thread busy is copied to the host and queued, and starts when
+ * a thread returns; PDHG keeps iterating meanwhile, as Algorithm 1's loop
+ * does while its crossover threads run.  The first call to return 1 wins: the others see
  * *cancel set, PDHG is stopped, and *winner receives its index.  When PDHG
  * reaches eps_rel without a winner, `fn` also runs on the calling thread from
  * the final iterate (idx -1) unless a snapshot was taken from that same
@@ -415,7 +442,12 @@ int pdhg_unrolled_forward(pdhg_ctx *ctx, int K, int ckpt_every,
  * dL/dc (n), dL/db (m) and dL/dA.values (nnz, A's CSR order), with the
  * scaling factors held fixed.  Segments between checkpoints are recomputed
  * with the forward kernels, which are deterministic, so the result does not
- * depend on ckpt_every.  The projection's subgradient is 0 at a tie. */
+ * depend on ckpt_every.  The projection's subgradient is 0 at a tie.
+ * The replay reads the context's current problem data, so a tape is valid
+ * only until the next pdhg_load, pdhg_configure, pdhg_set_values or
+ * pdhg_set_rhs_obj (with data) on its context: after any of them this call
+ * returns PDHG_E_STATE (a reload also frees the tape's device memory at
+ * once; the handle still needs pdhg_tape_free). */
 int pdhg_unrolled_backward(pdhg_tape *tape, const double *gxK, double *gc,
                            double *gb, double *gAval, int mem);
 /* Release a tape.  pdhg_destroy releases the device memory of the tapes of
@@ -440,6 +472,59 @@ int pdhg_cpu_steps(int64_t m, int64_t n, const int64_t *a_rp,
                    const double *at_v, const double *b, const double *c,
                    double tau, double sigma, int K, int threads, double *x,
                    double *y, double *seconds);
+
+/* ---- the CPU PDHG (host only) --------------------------------------------- */
+
+/* The restarted PDHG on the host's cores: the paper's CPU platform (Section
+ * 4.1 runs its PDHG on CPU cores next to the GPU one; Section 5 remarks that a
+ * fraction of the cores saturates the CPU's memory bandwidth).  The method is
+ * the GPU path's, in FP64 only: Ruiz equilibration, the power-iteration step
+ * size, the averaged or the reflected Halpern iteration, the FP64 KKT
+ * evaluation every eval_every iterations with the same snapshot, stop,
+ * restart and primal-weight decisions (Section 2's criteria, Algorithm 1's
+ * snapshot test).  Feasibility polishing, FP32 and graphs are GPU-only.  Work
+ * is split over a pool of `threads` host threads: the primal half over row
+ * ranges of A^T, the dual half over row ranges of A, each holding an equal
+ * share of the nonzeros; reductions are summed over fixed chunks of 4096 rows
+ * in chunk order, so the results do not depend on the thread count.  No GPU is
+ * used.  Every pointer is host memory; conventions as for the GPU calls (a
+ * context is not thread-safe except pdhg_cpu_cancel; inputs are copied). */
+typedef struct pdhg_cpu pdhg_cpu;
+int pdhg_cpu_create(int threads, pdhg_cpu **out);
+void pdhg_cpu_destroy(pdhg_cpu *ctx);
+const char *pdhg_cpu_last_error(const pdhg_cpu *ctx);
+/* Replace the thread pool (1 .. 1024 threads); the problem and iterate stay. */
+int pdhg_cpu_set_threads(pdhg_cpu *ctx, int threads);
+/* As pdhg_load (Section 2's primal problem; A^T must be A's exact
+ * transpose), host arrays only. */
+int pdhg_cpu_load(pdhg_cpu *ctx, int64_t m, int64_t n, int64_t nnz,
+                  const int64_t *a_rp, const int32_t *a_ci, const double *a_v,
+                  const int64_t *at_rp, const int32_t *at_ci,
+                  const double *at_v, const double *b, const double *c,
+                  const double *lb);
+/* As pdhg_configure; precision must be PDHG_FP64 and polish 0 (PDHG_E_ARG
+ * otherwise); use_graph is ignored.  Resets the iterate to zero. */
+int pdhg_cpu_configure(pdhg_cpu *ctx, const pdhg_params *p);
+/* As pdhg_iterate: up to max_iters more iterations, the evaluation at k = 0
+ * and every eval_every iterations; *status receives the pdhg_status. */
+int pdhg_cpu_iterate(pdhg_cpu *ctx, int64_t max_iters, int *status);
+int pdhg_cpu_cancel(pdhg_cpu *ctx);
+/* As pdhg_get_info; kkt is recomputed for the current iterate. */
+int pdhg_cpu_get_info(pdhg_cpu *ctx, pdhg_info *out);
+/* Unscaled current iterate x (n), y (m), z = max(0, c - A^T y) (n); any
+ * pointer may be NULL. */
+int pdhg_cpu_get_iterate(pdhg_cpu *ctx, double *x, double *y, double *z);
+int pdhg_cpu_get_scaling(pdhg_cpu *ctx, double *dr, double *dc);
+/* As pdhg_eval_log (8 doubles per evaluation). */
+int pdhg_cpu_eval_log(pdhg_cpu *ctx, double *out, int cap, int *count);
+int pdhg_cpu_snapshot_count(pdhg_cpu *ctx, int *count);
+int pdhg_cpu_snapshot(pdhg_cpu *ctx, int idx, pdhg_snapshot_info *info,
+                      double *x, double *y, double *z);
+/* Streaming read bandwidth of the host with `threads` threads: `reps` sums
+ * over an array of `bytes` bytes (first touched by the thread that reads each
+ * part), after one warm-up pass; *gb_s = bytes reps / time / 1e9.  The
+ * ceiling the CPU PDHG's iteration rate is compared with. */
+int pdhg_cpu_stream_bw(int threads, int64_t bytes, int reps, double *gb_s);
 
 /* ---- kernels for checking and measurement ------------------------------ */
 
@@ -497,6 +582,24 @@ int pdhg_plan_panels(int64_t rows, int64_t cols, const int64_t *rp,
 /* Number of column panels in use for matrix which (0 = A, 1 = A^T) of the
  * loaded problem, in *panels. */
 int pdhg_panel_count(pdhg_ctx *ctx, int which, int *panels);
+
+/* Random-gather rate of this GPU (measurement only; needs a context, not a
+ * problem).  One kernel streams n_gathers (index, value) pairs in the
+ * precision's value type, 4096 pairs per workgroup, with the SpMV's 16-byte
+ * loads (non-temporal when stream_nt = 1), gathers table[index] for each
+ * from a table of table_entries values and sums the products.  Workgroup w
+ * draws its indices uniformly at random (a fixed counter-based hash) from
+ * panel (w % 8) % panels of the table, the slice that the XCD it runs on
+ * gathers from in a panelled SpMV side.  After one warm-up launch, reps
+ * launches are timed with HIP events on the context's stream;
+ * *gathers_per_s = n_gathers reps / time.  This is the ceiling against which
+ * the step kernels' gathers are measured: the SpMVs make one random gather
+ * per nonzero, which the algorithmic byte count prices as 8 bytes but the
+ * memory system serves a cache line at a time.  Allocates and frees its
+ * buffers (about 12 n_gathers + 8 table_entries bytes in FP64). */
+int pdhg_gather_probe(pdhg_ctx *ctx, int64_t table_entries, int precision,
+                      int panels, int stream_nt, int64_t n_gathers, int reps,
+                      double *gathers_per_s);
 
 /* Enable (1) or disable (0) HIP-event timing of every iteration-kernel
  * launch (batches then run without graphs).  pdhg_kernel_times fills up to

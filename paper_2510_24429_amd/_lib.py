@@ -106,7 +106,9 @@ class KernelTime(C.Structure):
                 ("total_ms", C.c_double)]
 
 
-SNAP_CB = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.POINTER(SnapInfo))
+SNAP_CB = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.POINTER(SnapInfo),
+                      C.POINTER(C.c_double), C.POINTER(C.c_double),
+                      C.POINTER(C.c_double))
 CROSSOVER_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(SnapInfo),
                            C.POINTER(C.c_double), C.POINTER(C.c_double),
                            C.POINTER(C.c_double), C.POINTER(C.c_int32))
@@ -155,6 +157,8 @@ SIGNATURES = {
     "pdhg_unrolled_backward": (i32, [vp, vp, vp, vp, vp, i32]),
     "pdhg_tape_free": (None, [vp]),
     "pdhg_spmv": (i32, [vp, i32, i32, i32, vp, vp, i32]),
+    "pdhg_gather_probe": (i32, [vp, i64, i32, i32, i32, i64, i32,
+                                C.POINTER(C.c_double)]),
     "pdhg_set_tuning": (i32, [vp, C.c_char_p, i64]),
     "pdhg_bin_stats": (i32, [vp, i32, vp]),
     "pdhg_panel_count": (i32, [vp, i32, vp]),
@@ -162,6 +166,21 @@ SIGNATURES = {
     "pdhg_cpu_steps": (i32, [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double,
                              C.c_double, i32, i32, vp, vp, vp]),
     "pdhg_plan_panels": (i32, [i64, i64, vp, vp, i32, vp, i32, vp, vp, vp, i64]),
+    "pdhg_cpu_create": (i32, [i32, C.POINTER(vp)]),
+    "pdhg_cpu_destroy": (None, [vp]),
+    "pdhg_cpu_last_error": (C.c_char_p, [vp]),
+    "pdhg_cpu_set_threads": (i32, [vp, i32]),
+    "pdhg_cpu_load": (i32, [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+    "pdhg_cpu_configure": (i32, [vp, C.POINTER(Params)]),
+    "pdhg_cpu_iterate": (i32, [vp, i64, C.POINTER(i32)]),
+    "pdhg_cpu_cancel": (i32, [vp]),
+    "pdhg_cpu_get_info": (i32, [vp, C.POINTER(Info)]),
+    "pdhg_cpu_get_iterate": (i32, [vp, vp, vp, vp]),
+    "pdhg_cpu_get_scaling": (i32, [vp, vp, vp]),
+    "pdhg_cpu_eval_log": (i32, [vp, vp, i32, C.POINTER(i32)]),
+    "pdhg_cpu_snapshot_count": (i32, [vp, C.POINTER(i32)]),
+    "pdhg_cpu_snapshot": (i32, [vp, i32, C.POINTER(SnapInfo), vp, vp, vp]),
+    "pdhg_cpu_stream_bw": (i32, [i32, i64, i32, C.POINTER(C.c_double)]),
     "pdhg_profile": (i32, [vp, i32]),
     "pdhg_kernel_times": (i32, [vp, C.POINTER(KernelTime), i32,
                                 C.POINTER(i32), i32]),

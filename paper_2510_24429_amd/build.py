@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpdhg.so")
-SOURCES = ["host_csr.cpp", "kernels.hip", "pdhg.cpp", "cpu_steps.cpp"]
+SOURCES = ["host_csr.cpp", "kernels.hip", "pdhg.cpp", "cpu_steps.cpp", "cpu_pdhg.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

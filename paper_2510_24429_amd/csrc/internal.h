@@ -314,4 +314,14 @@ void launch_adj_gA(const DevCsr &A, const int32_t *rowidx, const T *y0,
                    const T *gy1, const T *gv, const T *x0, const T *x1,
                    T *gA, double tau, double sigma, hipStream_t s);
 
+// Gather-rate probe: indices of n streamed pairs, chunk per workgroup, each
+// workgroup confined to its panel of a table of `table` entries; the probe
+// kernel streams the pairs and sums val * table[idx] per workgroup into out.
+void launch_probe_fill(int32_t *idx, int64_t n, int64_t chunk, int64_t table,
+                       int P, uint64_t seed, hipStream_t s);
+template <typename T>
+void launch_gather_probe(const int32_t *idx, const T *val, const T *table,
+                         int64_t chunk, int64_t n, bool nt, T *out,
+                         hipStream_t s);
+
 }  // namespace pdhg

@@ -13,6 +13,7 @@
 
 #include <type_traits>
 
+#include "control.h"
 #include "internal.h"
 
 namespace pdhg {
@@ -846,37 +847,8 @@ __global__ __launch_bounds__(kWG) void k_kkt(KktArgs<T> a,
         }
 }
 
-__device__ double kkt_w(const double *S, double w) {
-    return sqrt(w * w * S[S_SP2] + S[S_SD2] / (w * w) + S[S_SG] * S[S_SG]);
-}
-
-// The measure a solve stops on and picks its candidate by: maxresid, or for
-// a feasibility phase the relative primal (1) or dual (2) residual alone.
-__device__ double stop_metric(const State *st, const double *S) {
-    return st->stop_on == 1 ? S[S_RELP] : st->stop_on == 2 ? S[S_RELD] : S[S_MAXR];
-}
-
-// Primal weight at a restart from the distances dx, dy travelled since the
-// previous restart: smoothing toward dy / dx in log space (omega_rule 0), or
-// PID control of log omega on the error e = log(omega dx / dy) (rule 1).
-// Unchanged when either distance is below 1e-10.
-__device__ double omega_update(State *st, double om, double dx, double dy) {
-    if (!(dx > 1e-10 && dy > 1e-10)) return om;
-    if (st->omega_rule == 1) {
-        const double e = log(om * dx / dy);
-        st->pid_int += e;
-        const double lw = log(om) - (st->pid_kp * e + st->pid_ki * st->pid_int +
-                                     st->pid_kd * (e - st->pid_eprev));
-        st->pid_eprev = e;
-        return exp(lw);
-    }
-    return exp(st->omega_theta * log(dy / dx) + (1.0 - st->omega_theta) * log(om));
-}
-
-// The decisions of one evaluation, taken by thread 0 after a fixed-order
-// finish of the partial sums.  Mirrors the CPU reference step by step:
-// statistics of both candidates, Algorithm 1's snapshot test on the better
-// one, the eps_rel stop, then the adaptive restart on KKT_omega.
+// One evaluation's decisions: a fixed-order finish of the partial sums in one
+// workgroup, then control_decide (control.h) on thread 0.
 __global__ __launch_bounds__(kWG) void k_control(State *st,
                                                  const double *__restrict__ partial,
                                                  int ncand, int batch,
@@ -914,204 +886,7 @@ __global__ __launch_bounds__(kWG) void k_control(State *st,
             if (tid == 0) tot[c][q] = sred[0];
             __syncthreads();
         }
-    if (tid != 0) return;
-
-    st->k += batch;
-    st->t_base += batch;
-    const long long k = st->k, t = st->t_base;
-    double om = st->omega;
-    bool finite = true;
-    for (int c = 0; c < ncand; ++c) {
-        double *S = st->stats[c];
-        const double *Q = tot[c];
-        S[S_NRP] = sqrt(Q[Q_RP2]);
-        S[S_NRD] = sqrt(Q[Q_RD2]);
-        S[S_RPINF] = Q[Q_RPMAX];
-        S[S_RDINF] = Q[Q_RDMAX];
-        S[S_POBJ] = Q[Q_CX];
-        S[S_DOBJ] = Q[Q_BY] + Q[Q_LZ];
-        S[S_RELP] = S[S_NRP] / (1.0 + st->nb);
-        S[S_RELD] = S[S_NRD] / (1.0 + st->nc);
-        S[S_RELG] = fabs(S[S_POBJ] - S[S_DOBJ]) /
-                    (1.0 + fabs(S[S_POBJ]) + fabs(S[S_DOBJ]));
-        double mr = S[S_RELP];
-        if (S[S_RELD] > mr) mr = S[S_RELD];
-        if (S[S_RELG] > mr) mr = S[S_RELG];
-        S[S_SP2] = Q[Q_SRP2];
-        S[S_SD2] = Q[Q_SRD2];
-        S[S_SG] = Q[Q_CX] - Q[Q_BY] - Q[Q_LZ];
-        S[S_DX2] = Q[Q_DX2];
-        S[S_DY2] = Q[Q_DY2];
-        const bool f = isfinite(S[S_RELP]) && isfinite(S[S_RELD]) &&
-                       isfinite(S[S_RELG]) && isfinite(S[S_SP2]) &&
-                       isfinite(S[S_SD2]) && isfinite(S[S_SG]);
-        S[S_MAXR] = f ? mr : NAN;
-        S[S_FIN] = f ? 1.0 : 0.0;
-        finite = finite && f;
-    }
-    st->last_ncand = ncand;
-    st->copy_pending = 0;
-    st->copy_avg = 0;
-    st->set_last = 0;
-    st->snap_n = 0;
-    st->polish_due = 0;
-
-    if (st->variant == 1) {
-        // reflected Halpern: candidate 1 is T(z); z itself is not projected,
-        // so T(z) is the reported point; restarts test ||z - T(z)||_omega
-        const double fx2 = tot[1][Q_FX2], fy2 = tot[1][Q_FY2];
-        st->fx2 = fx2;
-        st->fy2 = fy2;
-        const double r_cur = sqrt(om * fx2 + fy2 / om);
-        int restarted = 0;
-        if (!finite || !isfinite(r_cur)) {
-            st->status = PDHG_NUMERICAL;
-        } else {
-            const double mrb = st->stats[1][S_MAXR];
-            int fired = 0;
-            const int first = st->snap_count;
-            while (st->next_level < st->n_levels && mrb <= st->levels[st->next_level]) {
-                const int s = st->snap_count;
-                st->snap_level[s] = st->levels[st->next_level];
-                st->snap_iter[s] = k;
-                st->snap_mr[s] = mrb;
-                st->snap_cand_of[s] = 1;
-                ++st->snap_count;
-                ++st->next_level;
-                ++fired;
-                if (st->literal) break;
-            }
-            if (fired) {
-                st->snap_first = first;
-                st->snap_n = fired;
-                st->snap_cand = 1;
-            }
-            if (stop_metric(st, st->stats[1]) <= st->eps_rel) {
-                st->status = PDHG_CONVERGED;
-                st->returned_cand = 1;
-                st->copy_pending = 1;
-                st->copy_avg = 1;
-            } else if (initial) {
-                st->K_last = r_cur;
-            } else {
-                // a polishing attempt is decided on T(z) before a restart
-                st->polish_due = st->polish && st->stats[1][S_RELG] <= st->eps_rel &&
-                                 k >= st->next_polish;
-                st->polish_cand = 1;
-                const bool r = (r_cur <= st->beta_suff * st->K_last) ||
-                               (r_cur <= st->beta_nec * st->K_last && r_cur > st->K_prev) ||
-                               ((double)t >= st->beta_art * (double)k);
-                if (r) {
-                    const double *S = st->stats[1];
-                    om = omega_update(st, om, sqrt(S[S_DX2]), sqrt(S[S_DY2]));
-                    st->omega = om;
-                    st->tau = st->eta / om;
-                    st->sigma = st->eta * om;
-                    st->copy_pending = 1;
-                    st->copy_avg = 1;
-                    st->set_last = 1;
-                    st->t_base = 0;
-                    st->K_last = sqrt(om * fx2 + fy2 / om);
-                    st->K_prev = INFINITY;
-                    ++st->restarts;
-                    restarted = 1;
-                } else {
-                    st->K_prev = r_cur;
-                }
-            }
-        }
-        if (elog && st->n_log < st->log_cap) {
-            double *e = elog + 8 * st->n_log;
-            e[0] = (double)k;
-            e[1] = st->stats[0][S_MAXR];
-            e[2] = st->stats[1][S_MAXR];
-            e[3] = r_cur;
-            e[4] = st->K_last;
-            e[5] = (double)restarted;
-            e[6] = 1.0;
-            e[7] = om;
-            ++st->n_log;
-        }
-        return;
-    }
-
-    const int best = (ncand > 1 && stop_metric(st, st->stats[1]) <
-                                       stop_metric(st, st->stats[0])) ? 1 : 0;
-    double Kcur = kkt_w(st->stats[0], om);
-    double Kavg = ncand > 1 ? kkt_w(st->stats[1], om) : INFINITY;
-    int restarted = 0, cand = (Kavg < Kcur) ? 1 : 0;
-    if (initial) st->K_last = Kcur;
-
-    if (!finite) {
-        st->status = PDHG_NUMERICAL;
-    } else {
-        const double mrb = st->stats[best][S_MAXR];
-        int fired = 0;
-        const int first = st->snap_count;
-        while (st->next_level < st->n_levels && mrb <= st->levels[st->next_level]) {
-            const int s = st->snap_count;
-            st->snap_level[s] = st->levels[st->next_level];
-            st->snap_iter[s] = k;
-            st->snap_mr[s] = mrb;
-            st->snap_cand_of[s] = best;
-            ++st->snap_count;
-            ++st->next_level;
-            ++fired;
-            if (st->literal) break;
-        }
-        if (fired) {
-            st->snap_first = first;
-            st->snap_n = fired;
-            st->snap_cand = best;
-        }
-        if (stop_metric(st, st->stats[best]) <= st->eps_rel) {
-            st->status = PDHG_CONVERGED;
-            st->returned_cand = best;
-            if (best == 1) {
-                st->copy_pending = 1;
-                st->copy_avg = 1;
-            }
-        } else if (!initial) {
-            // a polishing attempt is decided on the better candidate before
-            // the restart test may replace it
-            st->polish_due = st->polish && st->stats[best][S_RELG] <= st->eps_rel &&
-                             k >= st->next_polish;
-            st->polish_cand = best;
-            const double *S = st->stats[cand];
-            const double Kc = cand ? Kavg : Kcur;
-            const bool r = (Kc <= st->beta_suff * st->K_last) ||
-                           (Kc <= st->beta_nec * st->K_last && Kc > st->K_prev) ||
-                           ((double)t >= st->beta_art * (double)k);
-            if (r) {
-                om = omega_update(st, om, sqrt(S[S_DX2]), sqrt(S[S_DY2]));
-                st->omega = om;
-                st->tau = st->eta / om;
-                st->sigma = st->eta * om;
-                st->copy_pending = 1;
-                st->copy_avg = cand;
-                st->set_last = 1;
-                st->t_base = 0;
-                st->K_last = kkt_w(S, om);
-                st->K_prev = INFINITY;
-                ++st->restarts;
-                restarted = 1;
-            } else {
-                st->K_prev = Kc;
-            }
-        }
-    }
-    if (elog && st->n_log < st->log_cap) {
-        double *e = elog + 8 * st->n_log;
-        e[0] = (double)k;
-        e[1] = st->stats[0][S_MAXR];
-        e[2] = ncand > 1 ? st->stats[1][S_MAXR] : NAN;
-        e[3] = Kcur;
-        e[4] = Kavg;
-        e[5] = (double)restarted;
-        e[6] = (double)cand;
-        e[7] = om;
-        ++st->n_log;
-    }
+    if (tid == 0) control_decide(st, tot, ncand, batch, initial, elog);
 }
 
 template <typename T>
@@ -1711,5 +1486,87 @@ template void launch_refine_update<double>(double *, double *, const double *,
                                            const double *, const double *,
                                            double, double, int64_t, int64_t,
                                            hipStream_t);
+
+// ============================================================ gather probe
+
+namespace {
+
+// splitmix64 finaliser (Steele, Lea and Flood's SplitMix generator): a
+// counter-based hash giving the probe its random indices.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Indices of the probe's stream: entry i belongs to workgroup i / chunk,
+// which gathers only from its panel (w % 8) % P of the table, as the row
+// blocks of a panelled SpMV side do (workgroup w runs on XCD w % 8).
+__global__ __launch_bounds__(kWG) void k_probe_fill(int32_t *idx, int64_t n,
+                                                    int64_t chunk,
+                                                    int64_t table, int P,
+                                                    uint64_t seed) {
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        const int64_t w = i / chunk;
+        const int p = (int)((w % 8) % P);
+        const int64_t lo = table * p / P, hi = table * (p + 1) / P;
+        idx[i] = (int32_t)(lo + (int64_t)(mix64(seed + (uint64_t)i) % (uint64_t)(hi - lo)));
+    }
+}
+
+// The SpMV's memory pattern without the row structure: workgroup w streams
+// the (index, value) pairs [w chunk, (w + 1) chunk) with 16-byte loads, four
+// per thread at a time, gathers table[index] for each and sums the products.
+template <typename T, bool NT>
+__global__ __launch_bounds__(kWG) void k_gather_probe(const int32_t *idx,
+                                                      const T *val,
+                                                      const T *table,
+                                                      int64_t chunk,
+                                                      int64_t n, T *out) {
+    __shared__ T sred[4];
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    T acc = 0;
+    for (int64_t p = b0 + 4 * (int64_t)threadIdx.x; p < b1; p += 4 * kWG) {
+        int j[4];
+        T a[4];
+        ld4<NT>(idx + p, j);
+        ld4<NT>(val + p, a);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (p + q < b1) acc += a[q] * table[j[q]];
+    }
+    acc = block_sum(acc, sred);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+}  // namespace
+
+void launch_probe_fill(int32_t *idx, int64_t n, int64_t chunk, int64_t table,
+                       int P, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe_fill, dim3(grid_for(n, kWG, 16384)), dim3(kWG),
+                       0, s, idx, n, chunk, table, P, seed);
+}
+
+template <typename T>
+void launch_gather_probe(const int32_t *idx, const T *val, const T *table,
+                         int64_t chunk, int64_t n, bool nt, T *out,
+                         hipStream_t s) {
+    const int g = (int)((n + chunk - 1) / chunk);
+    if (nt)
+        hipLaunchKernelGGL((k_gather_probe<T, true>), dim3(g), dim3(kWG), 0, s,
+                           idx, val, table, chunk, n, out);
+    else
+        hipLaunchKernelGGL((k_gather_probe<T, false>), dim3(g), dim3(kWG), 0, s,
+                           idx, val, table, chunk, n, out);
+}
+template void launch_gather_probe<double>(const int32_t *, const double *,
+                                          const double *, int64_t, int64_t,
+                                          bool, double *, hipStream_t);
+template void launch_gather_probe<float>(const int32_t *, const float *,
+                                         const float *, int64_t, int64_t,
+                                         bool, float *, hipStream_t);
 
 }  // namespace pdhg

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "job_queue.h"
 
 using namespace pdhg;
 
@@ -74,11 +75,13 @@ struct SnapMeta {
 
 struct CbItem {
     int idx;
+    int slot;                   // host copy the callback reads
     hipEvent_t ev;
     pdhg_snapshot_info info;    // copied at enqueue: the list may grow meanwhile
 };
 
 }  // namespace
+
 
 struct pdhg_ctx {
     int device = 0;
@@ -167,14 +170,16 @@ struct pdhg_ctx {
     double ref_DP = 1.0, ref_DD = 1.0, ref_target = -1.0;
 
     // callback thread
-    void (*cb)(void *, int, const pdhg_snapshot_info *) = nullptr;
+    pdhg_snapshot_cb cb = nullptr;
     void *cb_user = nullptr;
     std::thread cb_thread;
     std::mutex cb_mu;
     std::condition_variable cb_cv;
+    std::condition_variable cb_done_cv;   // a slot's callbacks have all run
     std::deque<CbItem> cb_queue;
     bool cb_stop = false;
-    std::vector<double *> host_snap;
+    std::vector<double *> host_snap;      // pinned host copy per slot
+    std::vector<int> host_snap_busy;      // queued or running callbacks per slot
 
     // graphs: one per (precision, eval_every, active pointers)
     hipGraphExec_t graph = nullptr;
@@ -182,6 +187,10 @@ struct pdhg_ctx {
 
     // live adjoint tapes (detached when the context is destroyed)
     std::vector<pdhg_tape *> tapes;
+    // generation of the problem data an adjoint replay reads (structure,
+    // values, b, c, l, scaling, relabeling): bumped by load, configure,
+    // set_values and set_rhs_obj; a tape records it at its forward pass
+    uint64_t data_gen = 0;
 
     // profiling
     bool profile = false;
@@ -193,11 +202,16 @@ struct pdhg_ctx {
 
 struct pdhg_tape {
     pdhg_ctx *ctx = nullptr;
+    uint64_t data_gen = 0;      // the context's data_gen at the forward pass
     int K = 0, ck = 0, prec = PDHG_FP64, nseg = 0;
     double tau = 0, sigma = 0;
     void *ckx = nullptr, *cky = nullptr, *ckax = nullptr;
     State *st = nullptr;
 };
+
+extern "C" {
+static void tape_release(pdhg_tape *tp);
+}
 
 namespace {
 
@@ -263,6 +277,46 @@ void vec_out(pdhg_ctx *c, double *dst, const double *src, bool rows, int mem) {
     copy_out(c, dst, tmp, k, mem);
 }
 
+// Device staging of one pdhg_spmv call: the input and output in internal
+// order, and their FP32 copies for the FP32 kernel.
+struct SpmvStage {
+    double *din = nullptr, *dout = nullptr;
+    float *i32 = nullptr, *o32 = nullptr;
+};
+
+// FP32 values of M (and of its panel copy, whose FP64 values are rewritten
+// from the same source) rounded from `vals` (nnz, M's order).
+void put_f32_values(pdhg_ctx *c, const DevCsr &M, const double *vals) {
+    launch_to_f32(M.v32, vals, M.nnz, c->stream);
+    if (M.pan) {
+        launch_gather(M.pan->v64, vals, M.pan_src, M.nnz, c->stream);
+        launch_to_f32(M.pan->v32, M.pan->v64, M.nnz, c->stream);
+    }
+}
+
+// out = M in for M = A (which 0) or A^T (which 1), through the staging
+// buffers st: gather `in` into internal order, run the binned SpMV kernel of
+// the requested precision, scatter back to the caller's order.  Returns
+// after the stream has finished.
+void spmv_staged(pdhg_ctx *c, int which, int scaled, int precision,
+                 const double *in, double *out, int mem, const SpmvStage &st) {
+    const DevCsr &M = which ? c->At : c->A;
+    vec_in(c, st.din, in, which == 1, mem);
+    if (precision == PDHG_FP32) {
+        launch_to_f32(st.i32, st.din, M.cols, c->stream);
+        // the FP32 kernel reads M.v32 (or its panel copy): put the loaded
+        // values there for an unscaled product, restore the scaled ones after
+        if (!scaled) put_f32_values(c, M, M.v_orig);
+        spmv_f32(M, st.i32, st.o32, c->stream);
+        launch_to_f64(st.dout, st.o32, M.rows, c->stream);
+        if (!scaled) put_f32_values(c, M, M.v64);
+    } else {
+        spmv_f64(M, scaled ? M.v64 : M.v_orig, st.din, st.dout, c->stream);
+    }
+    vec_out(c, out, st.dout, which == 0, mem);
+    sync(c);
+}
+
 // A caller array given by pointer and `mem`, staged to the host when needed.
 template <typename T>
 std::vector<T> to_host(pdhg_ctx *c, const T *p, int64_t count, int mem) {
@@ -320,6 +374,11 @@ void invalidate_graph(pdhg_ctx *c) {
 }
 
 void free_problem(pdhg_ctx *c) {
+    // tapes recorded on the data being dropped can no longer be replayed:
+    // free their device memory now (their handles stay valid for
+    // pdhg_tape_free, and pdhg_unrolled_backward refuses them)
+    ++c->data_gen;
+    for (pdhg_tape *tp : c->tapes) tape_release(tp);
     invalidate_graph(c);
     free_csr(c->A);
     free_csr(c->At);
@@ -368,9 +427,19 @@ void free_problem(pdhg_ctx *c) {
     dfree(c->log);
     dfree(c->slots);
     c->n_slots = 0;
+    {
+        // callbacks still queued or running read the host copies
+        std::unique_lock<std::mutex> lk(c->cb_mu);
+        c->cb_done_cv.wait(lk, [c] {
+            for (int b : c->host_snap_busy)
+                if (b) return false;
+            return true;
+        });
+    }
     for (double *h : c->host_snap)
         if (h) (void)hipHostFree(h);
     c->host_snap.clear();
+    c->host_snap_busy.clear();
     c->loaded = c->configured = false;
 }
 
@@ -809,7 +878,15 @@ void cb_worker(pdhg_ctx *c) {
         }
         (void)hipEventSynchronize(it.ev);
         (void)hipEventDestroy(it.ev);
-        if (c->cb) c->cb(c->cb_user, it.idx, &it.info);
+        if (c->cb) {
+            const double *x = c->host_snap[it.slot];
+            c->cb(c->cb_user, it.idx, &it.info, x, x + c->n, x + c->n + c->m);
+        }
+        {
+            std::lock_guard<std::mutex> lk(c->cb_mu);
+            --c->host_snap_busy[it.slot];
+        }
+        c->cb_done_cv.notify_all();
     }
 }
 
@@ -841,8 +918,17 @@ void start_snapshot_copies(pdhg_ctx *c, int before) {
     if (!c->cb || (int)c->snaps.size() == before) return;
     const int64_t len = 2 * c->n + c->m;
     const int slot = c->snaps[before].slot;
-    // (during refinement n_slots is 0 for the inner solves: size by the slot)
-    if ((int)c->host_snap.size() <= slot) c->host_snap.resize(slot + 1, nullptr);
+    {
+        // the slot's host copy is rewritten only after the callbacks still
+        // reading it (from an earlier solve) have returned
+        std::unique_lock<std::mutex> lk(c->cb_mu);
+        // (during refinement n_slots is 0 for the inner solves: size by the slot)
+        if ((int)c->host_snap.size() <= slot) {
+            c->host_snap.resize(slot + 1, nullptr);
+            c->host_snap_busy.resize(slot + 1, 0);
+        }
+        c->cb_done_cv.wait(lk, [c, slot] { return c->host_snap_busy[slot] == 0; });
+    }
     if (!c->host_snap[slot])
         HIPC(hipHostMalloc((void **)&c->host_snap[slot], len * sizeof(double), hipHostMallocDefault));
     hipEvent_t ready, done;
@@ -862,7 +948,8 @@ void start_snapshot_copies(pdhg_ctx *c, int before) {
                 HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
                 HIPC(hipEventRecord(e, c->copy_stream));
             }
-            c->cb_queue.push_back({i, e, c->snaps[i].info});
+            c->cb_queue.push_back({i, slot, e, c->snaps[i].info});
+            ++c->host_snap_busy[slot];
         }
     }
     c->cb_cv.notify_one();
@@ -1274,6 +1361,7 @@ int pdhg_set_values(pdhg_ctx *c, const double *a_v, int mem) {
     API_BEGIN(c)
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
     if (!a_v && c->nnz) return fail(c, PDHG_E_ARG, "null values");
+    ++c->data_gen;
     double *tmp = dmalloc<double>(c->nnz);
     copy_in(c, tmp, a_v, c->nnz, mem);
     launch_gather(c->A.v_orig, tmp, c->apos, c->nnz, c->stream);
@@ -1289,6 +1377,7 @@ int pdhg_set_values(pdhg_ctx *c, const double *a_v, int mem) {
 int pdhg_set_rhs_obj(pdhg_ctx *c, const double *b, const double *cv, int mem) {
     API_BEGIN(c)
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    if (b || cv) ++c->data_gen;
     if (b) vec_in(c, c->b_orig, b, true, mem);
     if (cv) vec_in(c, c->c_orig, cv, false, mem);
     apply_rhs_scaling(c);
@@ -1501,6 +1590,7 @@ int pdhg_configure(pdhg_ctx *c, const pdhg_params *p) {
             return fail(c, PDHG_E_ARG, "snapshot levels must be strictly descending");
     const double t0 = now_s();
     invalidate_graph(c);
+    ++c->data_gen;              // new scaling: earlier tapes are stale
     c->params = *p;
     c->levels.assign(p->levels, p->levels + p->n_levels);
     c->params.levels = nullptr;
@@ -1716,9 +1806,7 @@ int pdhg_snapshot(pdhg_ctx *c, int idx, pdhg_snapshot_info *info, double *x,
     API_END(c)
 }
 
-int pdhg_set_snapshot_callback(pdhg_ctx *c,
-                               void (*cb)(void *, int, const pdhg_snapshot_info *),
-                               void *user) {
+int pdhg_set_snapshot_callback(pdhg_ctx *c, pdhg_snapshot_cb cb, void *user) {
     API_BEGIN(c)
     c->cb = cb;
     c->cb_user = user;
@@ -1736,30 +1824,89 @@ int pdhg_spmv(pdhg_ctx *c, int which, int scaled, int precision,
     if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
     if (which < 0 || which > 1 || !in || !out) return fail(c, PDHG_E_ARG, "bad argument");
     const DevCsr &M = which ? c->At : c->A;
-    const int64_t nin = M.cols, nout = M.rows;
-    double *din = dmalloc<double>(nin), *dout = dmalloc<double>(nout);
-    // input in original order -> internal order
-    vec_in(c, din, in, which == 1, mem);
+    SpmvStage st;
+    st.din = dmalloc<double>(M.cols);
+    st.dout = dmalloc<double>(M.rows);
     if (precision == PDHG_FP32) {
-        float *i32 = dmalloc<float>(nin), *o32 = dmalloc<float>(nout);
-        launch_to_f32(i32, din, nin, c->stream);
-        if (!scaled) {
-            // FP32 copy of the loaded values
-            launch_to_f32(M.v32, M.v_orig, M.nnz, c->stream);
-        }
-        spmv_f32(M, i32, o32, c->stream);
-        launch_to_f64(dout, o32, nout, c->stream);
-        if (!scaled) launch_to_f32(M.v32, M.v64, M.nnz, c->stream);
-        sync(c);
-        dfree(i32);
-        dfree(o32);
-    } else {
-        spmv_f64(M, scaled ? M.v64 : M.v_orig, din, dout, c->stream);
+        st.i32 = dmalloc<float>(M.cols);
+        st.o32 = dmalloc<float>(M.rows);
     }
-    vec_out(c, out, dout, which == 0, mem);
-    sync(c);
-    dfree(din);
-    dfree(dout);
+    try {
+        spmv_staged(c, which, scaled, precision, in, out, mem, st);
+    } catch (...) {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(st.din), dfree(st.dout), dfree(st.i32), dfree(st.o32);
+        throw;
+    }
+    dfree(st.din), dfree(st.dout), dfree(st.i32), dfree(st.o32);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_gather_probe(pdhg_ctx *c, int64_t table_entries, int precision,
+                      int panels, int stream_nt, int64_t n_gathers, int reps,
+                      double *gathers_per_s) {
+    API_BEGIN(c)
+    if (!gathers_per_s || table_entries < 1 || table_entries >= ((int64_t)1 << 31) ||
+        (precision != PDHG_FP64 && precision != PDHG_FP32) ||
+        !(panels == 1 || panels == 2 || panels == 4 || panels == 8) ||
+        table_entries < panels || n_gathers < 1 || n_gathers >= ((int64_t)1 << 40) ||
+        reps < 1 || reps > 1000 || stream_nt < 0 || stream_nt > 1)
+        return fail(c, PDHG_E_ARG, "bad argument to pdhg_gather_probe");
+    const int64_t chunk = 4096;                   // pairs per workgroup
+    const int64_t npad = ((n_gathers + 3) & ~(int64_t)3) + 4;
+    const int64_t nwg = (n_gathers + chunk - 1) / chunk;
+    const size_t es = precision == PDHG_FP32 ? 4 : 8;
+    int32_t *idx = nullptr;
+    void *val = nullptr, *tab = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&] {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(idx);
+        if (val) (void)hipFree(val);
+        if (tab) (void)hipFree(tab);
+        if (out) (void)hipFree(out);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    try {
+        idx = dmalloc<int32_t>(npad);
+        HIPC(hipMalloc(&val, (size_t)npad * es));
+        HIPC(hipMalloc(&tab, (size_t)table_entries * es));
+        HIPC(hipMalloc(&out, (size_t)nwg * es));
+        launch_probe_fill(idx, npad, chunk, table_entries, panels, 0x5eedull, c->stream);
+        if (precision == PDHG_FP32) {
+            launch_fill32((float *)val, 1.0f, npad, c->stream);
+            launch_fill32((float *)tab, 0.5f, table_entries, c->stream);
+        } else {
+            launch_fill((double *)val, 1.0, npad, c->stream);
+            launch_fill((double *)tab, 0.5, table_entries, c->stream);
+        }
+        auto run = [&] {
+            if (precision == PDHG_FP32)
+                launch_gather_probe<float>(idx, (const float *)val, (const float *)tab,
+                                           chunk, n_gathers, stream_nt != 0,
+                                           (float *)out, c->stream);
+            else
+                launch_gather_probe<double>(idx, (const double *)val, (const double *)tab,
+                                            chunk, n_gathers, stream_nt != 0,
+                                            (double *)out, c->stream);
+        };
+        run();                                    // warm-up (table into the caches)
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        HIPC(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) run();
+        HIPC(hipEventRecord(e1, c->stream));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        *gathers_per_s = ms > 0.0f ? (double)n_gathers * reps / (ms * 1e-3) : 0.0;
+    } catch (...) {
+        release();
+        throw;
+    }
+    release();
     return PDHG_OK;
     API_END(c)
 }
@@ -1830,83 +1977,78 @@ int crossover_harness(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
         pdhg_snapshot_info info;
         std::vector<double> x, y, z;
     };
-    volatile int32_t cancel = 0;
+    // the cancel word the crossover routines poll: written and read with
+    // atomic operations by the library, read as a volatile int32 by callers
+    alignas(4) int32_t cancel_word = 0;
+    auto cancelled = [&] { return __atomic_load_n(&cancel_word, __ATOMIC_ACQUIRE) != 0; };
     std::atomic<int> win{-2};
-    std::atomic<int> running{0};
-    std::mutex mu;
-    std::condition_variable cv;
-    std::vector<std::thread> threads;
-    auto run_job = [&](std::shared_ptr<Job> j) {
-        const int ok = fn(user, j->idx, &j->info, j->x.data(), j->y.data(),
-                          j->z.data(), &cancel);
+    JobQueue jobs(max_threads, cancelled);
+    auto run_job = [&](const std::shared_ptr<Job> &jb) {
+        const int ok = fn(user, jb->idx, &jb->info, jb->x.data(), jb->y.data(),
+                          jb->z.data(), (const volatile int32_t *)&cancel_word);
         if (ok == 1) {
             int expected = -2;
-            if (win.compare_exchange_strong(expected, j->idx)) {
-                cancel = 1;
+            if (win.compare_exchange_strong(expected, jb->idx)) {
+                __atomic_store_n(&cancel_word, 1, __ATOMIC_RELEASE);
                 c->cancel_flag.store(1);
+                jobs.notify();
             }
         }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            running.fetch_sub(1);
-        }
-        cv.notify_all();
     };
     auto fetch = [&](int idx) {
-        auto j = std::make_shared<Job>();
-        j->idx = idx;
-        j->x.resize((size_t)c->n);
-        j->y.resize((size_t)c->m);
-        j->z.resize((size_t)c->n);
+        auto jb = std::make_shared<Job>();
+        jb->idx = idx;
+        jb->x.resize((size_t)c->n);
+        jb->y.resize((size_t)c->m);
+        jb->z.resize((size_t)c->n);
         if (idx >= 0) {
             const SnapMeta &sm = c->snaps[idx];
-            j->info = sm.info;
+            jb->info = sm.info;
             const double *base = c->slots + (int64_t)sm.slot * (2 * c->n + c->m);
-            HIPC(hipMemcpyAsync(j->x.data(), base, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            HIPC(hipMemcpyAsync(j->y.data(), base + c->n, c->m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            HIPC(hipMemcpyAsync(j->z.data(), base + c->n + c->m, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipMemcpyAsync(jb->x.data(), base, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipMemcpyAsync(jb->y.data(), base + c->n, c->m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipMemcpyAsync(jb->z.data(), base + c->n + c->m, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             sync(c);
         }
-        return j;
+        return jb;
     };
-    auto launch = [&](std::shared_ptr<Job> j) {
-        std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] {
-            return max_threads == 0 || running.load() < max_threads || cancel;
-        });
-        if (cancel) return;
-        running.fetch_add(1);
-        threads.emplace_back(run_job, j);
+    // a snapshot is copied to the host and queued; the PDHG loop goes on
+    auto queue = [&](int idx) {
+        if (cancelled()) return;
+        auto jb = fetch(idx);
+        jobs.push([&run_job, jb] { run_job(jb); });
     };
     int st = c->status;
     try {
-        for (size_t i = 0; i < c->snaps.size() && !cancel; ++i) launch(fetch((int)i));
+        for (size_t i = 0; i < c->snaps.size() && !cancelled(); ++i) queue((int)i);
         c->snap_hook = [&](int before) {
-            for (int i = before; i < (int)c->snaps.size() && !cancel; ++i)
-                launch(fetch(i));
+            for (int i = before; i < (int)c->snaps.size() && !cancelled(); ++i)
+                queue(i);
         };
         st = drive();
         c->snap_hook = nullptr;
         // Algorithm 1's last line: crossover from the converged iterate on
         // this thread, unless that iterate was already handed out
-        if (!cancel && st == PDHG_CONVERGED &&
+        if (!cancelled() && st == PDHG_CONVERGED &&
             (c->snaps.empty() || c->snaps.back().info.iter != c->k_host)) {
-            auto j = fetch(-1);
-            pdhg_get_iterate(c, j->x.data(), j->y.data(), j->z.data(), PDHG_MEM_HOST);
-            std::memset(&j->info, 0, sizeof j->info);
-            j->info.level = c->params.eps_rel;
-            j->info.iter = c->k_host;
-            j->info.t_wall = now_s() - c->t_start;
-            running.fetch_add(1);
-            run_job(j);
+            auto jb = fetch(-1);
+            pdhg_get_iterate(c, jb->x.data(), jb->y.data(), jb->z.data(), PDHG_MEM_HOST);
+            std::memset(&jb->info, 0, sizeof jb->info);
+            jb->info.level = c->params.eps_rel;
+            jb->info.iter = c->k_host;
+            jb->info.t_wall = now_s() - c->t_start;
+            jobs.add_external();
+            run_job(jb);
+            jobs.end_external();
         }
     } catch (...) {
         c->snap_hook = nullptr;
-        cancel = 1;
-        for (auto &t : threads) t.join();
+        __atomic_store_n(&cancel_word, 1, __ATOMIC_RELEASE);
+        jobs.notify();
+        jobs.close_and_join();
         throw;
     }
-    for (auto &t : threads) t.join();
+    jobs.close_and_join();
     c->cancel_flag.store(0);
     if (winner) *winner = win.load();
     if (status) *status = st;
@@ -2403,6 +2545,7 @@ int pdhg_unrolled_forward(pdhg_ctx *c, int K, int ckpt_every, int precision,
     *tape = nullptr;
     pdhg_tape *tp = new pdhg_tape();
     tp->ctx = c;
+    tp->data_gen = c->data_gen;
     tp->K = K;
     tp->ck = std::min(ckpt_every, K);
     tp->prec = precision;
@@ -2438,6 +2581,11 @@ int pdhg_unrolled_backward(pdhg_tape *tp, const double *gxK, double *gc,
     pdhg_ctx *c = tp->ctx;
     API_BEGIN(c)
     if (!gxK || !gc || !gb || !gAval) return fail(c, PDHG_E_ARG, "null argument");
+    if (tp->data_gen != c->data_gen || !tp->ckx)
+        return fail(c, PDHG_E_STATE,
+                    "the problem data changed since this tape's forward pass "
+                    "(load, configure, set_values or set_rhs_obj); run the "
+                    "forward pass again");
     if (tp->prec == PDHG_FP32)
         unrolled_backward_T<float>(tp, gxK, gc, gb, gAval, mem);
     else

@@ -80,23 +80,35 @@ class Solver:
         ctx = C.c_void_p()
         L.check(self.lib.pdhg_create(device, stream, C.byref(ctx)))
         self.ctx = ctx
-        for k, v in (tuning or {}).items():
-            L.check(self.lib.pdhg_set_tuning(self.ctx, k.encode(), int(v)), self.ctx)
-        args = [_Arg(a_rp, np.int64, self.m + 1, "a_rp"),
-                _Arg(a_ci, np.int32, nnz, "a_ci"),
-                _Arg(a_v, np.float64, nnz, "a_v"),
-                _Arg(at_rp, np.int64, self.n + 1, "at_rp"),
-                _Arg(at_ci, np.int32, nnz, "at_ci"),
-                _Arg(at_v, np.float64, nnz, "at_v"),
-                _Arg(b, np.float64, self.m, "b"),
-                _Arg(c, np.float64, self.n, "c"),
-                _Arg(lb, np.float64, self.n, "lb")]
-        mem = _same_mem(*args)
-        L.check(self.lib.pdhg_load(self.ctx, self.m, self.n, nnz,
-                                   *[a.ptr for a in args], mem), self.ctx)
         self._keep = None
         self._cb = None
         self._tapes = []
+        for k, v in (tuning or {}).items():
+            L.check(self.lib.pdhg_set_tuning(self.ctx, k.encode(), int(v)), self.ctx)
+        self.load(m, n, a_rp, a_ci, a_v, at_rp, at_ci, at_v, b, c, lb)
+
+    def load(self, m, n, a_rp, a_ci, a_v, at_rp, at_ci, at_v, b, c, lb=None):
+        """pdhg_load: (re)load a problem into this context."""
+        m, n = int(m), int(n)
+        nnz = int(len(a_v)) if not _is_torch(a_v) else int(a_v.numel())
+        args = [_Arg(a_rp, np.int64, m + 1, "a_rp"),
+                _Arg(a_ci, np.int32, nnz, "a_ci"),
+                _Arg(a_v, np.float64, nnz, "a_v"),
+                _Arg(at_rp, np.int64, n + 1, "at_rp"),
+                _Arg(at_ci, np.int32, nnz, "at_ci"),
+                _Arg(at_v, np.float64, nnz, "at_v"),
+                _Arg(b, np.float64, m, "b"),
+                _Arg(c, np.float64, n, "c"),
+                _Arg(lb, np.float64, n, "lb")]
+        mem = _same_mem(*args)
+        L.check(self.lib.pdhg_load(self.ctx, m, n, nnz,
+                                   *[a.ptr for a in args], mem), self.ctx)
+        self.m, self.n, self.nnz = m, n, nnz
+        return self
+
+    def load_lp(self, lp, lb=None):
+        return self.load(lp.m, lp.n, lp.a_rp, lp.a_ci, lp.a_v, lp.at_rp,
+                         lp.at_ci, lp.at_v, lp.b, lp.c, lb=lb)
 
     @classmethod
     def from_lp(cls, lp, lb=None, **kw) -> "Solver":
@@ -216,10 +228,20 @@ class Solver:
                 self.ctx)
         return inf.asdict(), x, y, z
 
-    def set_snapshot_callback(self, fn):
-        """fn(idx, info_dict) runs on a library thread after the host copy."""
-        def _cb(user, idx, info):
-            fn(idx, info.contents.asdict())
+    def set_snapshot_callback(self, fn, with_vectors: bool = False):
+        """fn(idx, info_dict) -- or, with_vectors, fn(idx, info_dict, x, y, z)
+        with copies of the snapshot's unscaled vectors -- runs on a library
+        thread after the snapshot's host copy."""
+        n, m = self.n, self.m
+
+        def _cb(user, idx, info, px, py, pz):
+            if with_vectors:
+                fn(idx, info.contents.asdict(),
+                   np.ctypeslib.as_array(px, shape=(n,)).copy(),
+                   np.ctypeslib.as_array(py, shape=(m,)).copy(),
+                   np.ctypeslib.as_array(pz, shape=(n,)).copy())
+            else:
+                fn(idx, info.contents.asdict())
         self._cb = L.SNAP_CB(_cb)
         L.check(self.lib.pdhg_set_snapshot_callback(self.ctx, self._cb, None), self.ctx)
 
@@ -297,6 +319,17 @@ class Solver:
         L.check(self.lib.pdhg_spmv(self.ctx, which, int(scaled), precision, a.ptr,
                                    po, mem), self.ctx)
         return out
+
+    def gather_probe(self, table_entries: int, precision: int = L.FP64,
+                     panels: int = 1, stream_nt: int = 0,
+                     n_gathers: int = 1 << 25, reps: int = 5) -> float:
+        """pdhg_gather_probe: random gathers per second from a table of
+        table_entries values, each XCD confined to 1/panels of it."""
+        r = C.c_double(0.0)
+        L.check(self.lib.pdhg_gather_probe(self.ctx, int(table_entries), precision,
+                                           panels, stream_nt, int(n_gathers), reps,
+                                           C.byref(r)), self.ctx)
+        return r.value
 
     def bin_stats(self, which: int):
         out = np.zeros(3, dtype=np.int64)

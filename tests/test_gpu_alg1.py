@@ -118,3 +118,37 @@ def test_refined_harness_without_winner_runs_final_crossover(Solver, oracle):
     assert (-1, 1e-8) in seen
     assert sorted(l for i, l in seen if i >= 0) == [1e-4, 1e-2]
     assert oracle.kkt(lp, x, y)["maxresid"] <= 1e-8
+
+
+def test_busy_threads_do_not_hold_up_pdhg(Solver):
+    """With one crossover thread and slow crossovers, later snapshots queue
+    and PDHG keeps iterating (Algorithm 1's loop runs while its threads do):
+    the solve's own time stays far below the crossovers' total, and every
+    snapshot still gets its crossover, one at a time."""
+    lp = lpgen.make("uniform_m500_n1k")
+    levels = [1e-2, 1e-3, 1e-4, 1e-5]
+    starts, lock = [], threading.Lock()
+    active = [0]
+
+    def crossover(idx, info, x, y, z, cancelled):
+        with lock:
+            active[0] += 1
+            starts.append((idx, active[0]))
+        time.sleep(0.4)
+        with lock:
+            active[0] -= 1
+        return False
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-6, levels=levels)
+        t0 = time.time()
+        winner, status = s.concurrent_crossover(crossover, max_threads=1)
+        dt = time.time() - t0
+        t_iter = s.info()["t_iter"]
+    assert winner == -2 and status == 1
+    assert sorted(i for i, _ in starts if i >= 0) == [0, 1, 2, 3]
+    # the thread limit holds for the snapshot crossovers; the final one runs
+    # on the calling thread beside them
+    assert all(a <= 2 for _, a in starts)
+    assert dt >= 4 * 0.4
+    assert t_iter < 0.8, t_iter

@@ -29,6 +29,17 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def elem(a, b):
+    """Largest entry-wise difference relative to the largest entry of b: a
+    single wrong entry shows here even when the norm-wise error is small."""
+    s = np.max(np.abs(b)) if b.size else 0.0
+    return np.max(np.abs(a - b)) / (s if s > 0 else 1.0) if a.size else 0.0
+
+
+def err(a, b):
+    return max(rel(a, b), elem(a, b))
+
+
 def _integer_lp(seed=0):
     """Integer-valued CSR spanning every bin: empty rows, short rows, rows
     between the tiles, single-workgroup rows and rows long enough to split."""
@@ -91,6 +102,15 @@ def test_spmv_bins_bitwise_on_integers(Solver, split, panels):
     assert np.array_equal(s.spmv(1, y, scaled=True), aty)
     assert np.array_equal(s.spmv(0, x, scaled=True, precision=1), ax)
     assert np.array_equal(s.spmv(1, y, scaled=True, precision=1), aty)
+    # after configure the scaled values differ from the loaded ones; the
+    # loaded-value products (also the FP32 ones, whose panel copy is swapped
+    # in for the call) stay A x and A^T y, and the scaled ones are restored
+    s.configure(eps_rel=1e-6)
+    sc0 = s.spmv(0, x, scaled=True, precision=1)
+    for prec in (0, 1):
+        assert np.array_equal(s.spmv(0, x, precision=prec), ax)
+        assert np.array_equal(s.spmv(1, y, precision=prec), aty)
+    assert np.array_equal(s.spmv(0, x, scaled=True, precision=1), sc0)
     s.close()
 
 
@@ -123,7 +143,7 @@ def _trace_parity(Solver, oracle, lp, K, l=None, tuning=None, **kw):
         for k in range(K):
             s.iterate(1)
             x, y, _ = s.get_iterate()
-            worst = max(worst, rel(x, ref.trace_x[k]), rel(y, ref.trace_y[k]))
+            worst = max(worst, err(x, ref.trace_x[k]), err(y, ref.trace_y[k]))
     return worst
 
 
@@ -234,7 +254,7 @@ def test_full_solve_kkt_and_snapshots(Solver, oracle, variant, panels):
         info, x, y, z = s.snapshot(i)
         assert info["level"] == sn["level"] and info["iter"] == sn["iter"]
         assert abs(info["maxresid"] - sn["maxresid"]) <= 1e-12
-        assert rel(x, ref.snap_x[i]) <= 1e-8 and rel(y, ref.snap_y[i]) <= 1e-8
+        assert err(x, ref.snap_x[i]) <= 1e-8 and err(y, ref.snap_y[i]) <= 1e-8
         assert np.max(np.abs(z - ref.snap_z[i])) <= 1e-8 * (1 + np.max(np.abs(ref.snap_z[i])))
         # the snapshot satisfies the level on the original data (CPU recompute)
         kk = oracle.kkt(lp, x, y)
@@ -321,22 +341,33 @@ def test_cancel_and_time_limit(Solver):
         assert time.time() - t0 < 30
 
 
-def test_snapshot_callback(Solver):
+def test_snapshot_callback(Solver, oracle):
+    """The callback receives each snapshot's info and its unscaled vectors,
+    equal to what pdhg_snapshot returns, in emission order, also on a second
+    solve of the same context (the host copies are reused)."""
     lp = lpgen.make("uniform_m500_n1k")
-    seen = []
-    ev = threading.Event()
-
-    def cb(idx, info):
-        seen.append((idx, info["level"]))
-        if len(seen) == 3:
-            ev.set()
-
+    levels = [1e-2, 1e-4, 1e-6]
     with Solver.from_lp(lp) as s:
-        s.configure(eps_rel=1e-6, levels=[1e-2, 1e-4, 1e-6])
-        s.set_snapshot_callback(cb)
-        assert s.solve() == 1
-        assert ev.wait(10)
-    assert sorted(seen) == [(0, 1e-2), (1, 1e-4), (2, 1e-6)]
+        for rnd in range(2):
+            seen = []
+            ev = threading.Event()
+
+            def cb(idx, info, x, y, z):
+                seen.append((idx, info, x, y, z))
+                if len(seen) == 3:
+                    ev.set()
+
+            s.configure(eps_rel=1e-6, levels=levels)
+            s.set_snapshot_callback(cb, with_vectors=True)
+            assert s.solve() == 1
+            assert ev.wait(10)
+            assert [(i, inf["level"]) for i, inf, *_ in seen] == list(enumerate(levels))
+            for idx, info, x, y, z in seen:
+                ref_info, rx, ry, rz = s.snapshot(idx)
+                assert info == ref_info
+                assert np.array_equal(x, rx) and np.array_equal(y, ry)
+                assert np.array_equal(z, rz)
+                assert oracle.kkt(lp, x, y)["maxresid"] <= info["level"]
 
 
 def test_bad_inputs_rejected(Solver):
@@ -353,80 +384,149 @@ def test_bad_inputs_rejected(Solver):
             s.configure(levels=[1e-6, 1e-4])
 
 
+def _full_size_windows(Solver, oracle, lp, panels, kw, K_step, K_graph,
+                       tag, graph_every=64):
+    """Full-size parity in the benchmark's launch configuration (column
+    panels and streamed-load kind chosen from the sizes):
+      - Ruiz factors bitwise;
+      - K_step single iterations (no graph), each iterate element-wise
+        within 1e-10 of the oracle's, with their evaluations and restart
+        decisions at eval_every = 2;
+      - K_graph iterations as replayed batches of graph_every iterations
+        (the graph the benchmark times, with its in-graph evaluation and
+        restart; the benchmark's batch is 64), the iterate after the last
+        batch element-wise within 1e-10 and the evaluation log's restart
+        flags equal."""
+    dr, dc, _ = oracle.ruiz(lp, 10)
+    print(f"[full-size] {tag}: oracle runs", flush=True)
+    kw1 = dict(kw, eval_every=2)
+    ref1 = oracle.solve(lp, trace_k=K_step, max_iters=K_step, **kw1)
+    kw2 = dict(kw, eval_every=graph_every)
+    print(f"[full-size] {tag}: oracle run of {K_graph} iterations", flush=True)
+    ref2 = oracle.solve(lp, max_iters=K_graph, **kw2)
+    with Solver.from_lp(lp) as s:
+        assert (s.panel_count(0), s.panel_count(1)) == panels
+        s.configure(**kw1)
+        gdr, gdc = s.get_scaling()
+        assert np.array_equal(gdr, dr) and np.array_equal(gdc, dc)
+        print(f"[full-size] {tag}: {K_step} single steps", flush=True)
+        for k in range(K_step):
+            s.iterate(1)
+            x, y, _ = s.get_iterate()
+            assert err(x, ref1.trace_x[k]) <= 1e-10, k
+            assert err(y, ref1.trace_y[k]) <= 1e-10, k
+        log = s.eval_log()
+        assert np.array_equal(log[:, 5], ref1.eval_log[:, 5])
+        assert np.allclose(log[:, 1:5], ref1.eval_log[:, 1:5], rtol=1e-9, atol=0,
+                           equal_nan=True)
+        print(f"[full-size] {tag}: {K_graph} iterations in graph batches", flush=True)
+        s.configure(**kw2)
+        s.iterate(K_graph)
+        x, y, _ = s.get_iterate()
+        log = s.eval_log()
+    assert log.shape[0] == ref2.eval_log.shape[0] == K_graph // graph_every + 1
+    assert np.array_equal(log[:, 0], ref2.eval_log[:, 0])
+    assert np.array_equal(log[:, 5], ref2.eval_log[:, 5])
+    assert np.allclose(log[:, 1:5], ref2.eval_log[:, 1:5], rtol=1e-9, atol=0,
+                       equal_nan=True)
+    assert err(x, ref2.x) <= 1e-10, err(x, ref2.x)
+    assert err(y, ref2.y) <= 1e-10, err(y, ref2.y)
+
+
+@pytest.mark.timeout(900)
 def test_full_size_multicommodity_parity(Solver, oracle):
     """The multicommodity workload at full size (m=1.35M, n=4.95M,
-    nnz=14.55M) in the benchmark's launch configuration (column panels and
-    non-temporal streaming chosen from the sizes): Ruiz factors bitwise, and
-    the first iterations plus evaluations with a restart decision."""
+    nnz=14.55M): 8 column panels for the dual step, non-temporal streaming.
+    The step size and primal weight are computed (power iteration)."""
     lp = lpgen.make("mcf_150knodes_600karcs_k8")
-    dr, dc, _ = oracle.ruiz(lp, 10)
-    K = 4
-    kw = dict(eps_rel=1e-8, eval_every=2, eta=0.5, omega0=1.3, variant=1)
-    ref = oracle.solve(lp, trace_k=K, max_iters=K, **kw)
-    with Solver.from_lp(lp) as s:
-        assert s.panel_count(0) == 8
-        s.configure(**kw)
-        gdr, gdc = s.get_scaling()
-        assert np.array_equal(gdr, dr) and np.array_equal(gdc, dc)
-        for k in range(K):
-            s.iterate(1)
-            x, y, _ = s.get_iterate()
-            assert rel(x, ref.trace_x[k]) <= 1e-10, k
-            assert rel(y, ref.trace_y[k]) <= 1e-10, k
-        log = s.eval_log()
-        assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
-        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0,
-                           equal_nan=True)
+    _full_size_windows(Solver, oracle, lp, (8, 1),
+                       dict(eps_rel=1e-8, variant=1), 4, 64, "multicommodity")
 
 
+@pytest.mark.timeout(900)
 def test_full_size_coupled_parity(Solver, oracle):
-    """The largest workload at full size (m=5M, n=20M, nnz=110M) in its
-    launch configuration (8 column panels for the dual step, 4 for the
-    primal step, non-temporal streaming): Ruiz factors bitwise, and the first
-    iterations plus evaluations against the oracle."""
+    """The largest workload at full size (m=5M, n=20M, nnz=110M): 8 column
+    panels for the dual step, 4 for the primal step, non-temporal streaming.
+    The serial oracle takes seconds per iteration here, so the step size and
+    primal weight are fixed (no 100-step power iteration) and the graph
+    window is two batches of 8 iterations."""
     lp = lpgen.make("coupled_m5m_n20m")
-    dr, dc, _ = oracle.ruiz(lp, 10)
-    K = 3
-    kw = dict(eps_rel=1e-8, eval_every=2, eta=0.5, omega0=1.3, variant=1)
-    ref = oracle.solve(lp, trace_k=K, max_iters=K, **kw)
-    with Solver.from_lp(lp) as s:
-        assert (s.panel_count(0), s.panel_count(1)) == (8, 4)
-        s.configure(**kw)
-        gdr, gdc = s.get_scaling()
-        assert np.array_equal(gdr, dr) and np.array_equal(gdc, dc)
-        for k in range(K):
-            s.iterate(1)
-            x, y, _ = s.get_iterate()
-            assert rel(x, ref.trace_x[k]) <= 1e-10, k
-            assert rel(y, ref.trace_y[k]) <= 1e-10, k
-        log = s.eval_log()
-        assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
-        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0,
-                           equal_nan=True)
+    _full_size_windows(Solver, oracle, lp, (8, 4),
+                       dict(eps_rel=1e-8, variant=1, eta=0.5, omega0=1.3), 3, 16,
+                       "coupled", graph_every=8)
 
 
+@pytest.mark.timeout(900)
 def test_full_size_powerlaw_parity(Solver, oracle):
-    """The benchmark workload at full size (m=200k, n=1M, nnz~9.4M): Ruiz
-    factors bitwise, and the first iterations plus one evaluation with a
-    restart against the oracle."""
+    """The power-law workload at full size (m=200k, n=1M, nnz~9.4M):
+    power-iteration estimate and initial primal weight within 1e-13 of the
+    oracle's; the first 100 iterations (both variants' bench default, the
+    Halpern one, with one evaluation at 64) element-wise within 1e-10;
+    128 iterations as two replayed graph batches."""
     lp = lpgen.make("powerlaw_m200k_n1m")
+    kw = dict(eps_rel=1e-8, variant=1)
     dr, dc, _ = oracle.ruiz(lp, 10)
-    K = 4
-    kw = dict(eps_rel=1e-8, eval_every=2, eta=0.5, omega0=1.3)
-    ref = oracle.solve(lp, trace_k=K, max_iters=K, **kw)
+    K = 100
+    print("[full-size] power-law: oracle run", flush=True)
+    ref = oracle.solve(lp, trace_k=K, max_iters=128, **kw)
     with Solver.from_lp(lp) as s:
+        assert (s.panel_count(0), s.panel_count(1)) == (4, 1)
         s.configure(**kw)
+        inf = s.info()
+        for key in ("sigma_hat", "omega0", "eta"):
+            assert abs(inf[key] - ref.info[key]) <= 1e-13 * abs(ref.info[key]), key
         gdr, gdc = s.get_scaling()
         assert np.array_equal(gdr, dr) and np.array_equal(gdc, dc)
+        print("[full-size] power-law: 100 single steps", flush=True)
         for k in range(K):
             s.iterate(1)
             x, y, _ = s.get_iterate()
-            assert rel(x, ref.trace_x[k]) <= 1e-10, k
-            assert rel(y, ref.trace_y[k]) <= 1e-10, k
-        log = s.eval_log()
+            assert err(x, ref.trace_x[k]) <= 1e-10, k
+            assert err(y, ref.trace_y[k]) <= 1e-10, k
+        s.iterate(128 - K)
+        x, y, _ = s.get_iterate()
+        assert err(x, ref.x) <= 1e-10 and err(y, ref.y) <= 1e-10
+        log1 = s.eval_log()
+        print("[full-size] power-law: 128 iterations in graph batches", flush=True)
+        s.configure(**kw)
+        s.iterate(128)
+        x, y, _ = s.get_iterate()
+        log2 = s.eval_log()
+    for log in (log1, log2):
+        assert log.shape == ref.eval_log.shape
+        assert np.array_equal(log[:, 0], ref.eval_log[:, 0])
         assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
-        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0,
-                           equal_nan=True)
+        assert np.allclose(log[:, 1:5], ref.eval_log[:, 1:5], rtol=1e-9, atol=0)
+    assert err(x, ref.x) <= 1e-10 and err(y, ref.y) <= 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_mid_size_full_solve_parity(Solver, oracle):
+    """A full solve of a 20k x 60k LP (8 nonzeros per column, about 5.5k and
+    11k iterations) in both variants: the same iteration count, restarts and
+    snapshot iterations as the oracle, final relative KKT errors within
+    1e-12."""
+    lp = lpgen.planted_uniform(m=20_000, n=60_000, k=8, seed=31)
+    for variant in (0, 1):
+        levels = [1e-3, 1e-5]
+        ref = oracle.solve(lp, levels=levels, eps_rel=1e-6, variant=variant)
+        with Solver.from_lp(lp) as s:
+            s.configure(levels=levels, eps_rel=1e-6, variant=variant)
+            st = s.solve()
+            inf = s.info()
+            log = s.eval_log()
+            snaps = [s.snapshot(i)[0] for i in range(s.snapshot_count())]
+        print(f"[mid-size] variant {variant}: {inf['iters']} iterations, "
+              f"{inf['restarts']} restarts (oracle {ref.info['iters']}, "
+              f"{ref.info['restarts']})", flush=True)
+        assert st == 1 and ref.info["status"] == 1
+        assert inf["iters"] == ref.info["iters"]
+        assert inf["restarts"] == ref.info["restarts"]
+        assert np.array_equal(log[:, 5], ref.eval_log[:, 5])
+        for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
+            assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
+        assert [(sn["level"], sn["iter"]) for sn in snaps] == \
+            [(sn["level"], sn["iter"]) for sn in ref.snaps]
 
 
 # ------------------------------------------------- feasibility polishing
@@ -484,7 +584,7 @@ def test_polishing_success_matches_oracle(Solver, oracle):
     for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
         assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
     x, y, _ = s.get_iterate()
-    assert rel(x, ref.x) <= 1e-10 and rel(y, ref.y) <= 1e-10
+    assert err(x, ref.x) <= 1e-10 and err(y, ref.y) <= 1e-10
     kk = oracle.kkt(lp, x, y)
     assert kk["maxresid"] <= 1e-8
     s.close()

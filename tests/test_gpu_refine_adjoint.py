@@ -180,6 +180,7 @@ def test_unrolled_fp32_within_gate(Solver, oracle):
     assert rel(gc, gc_or) <= 1e-3 and rel(gb, gb_or) <= 1e-3 and rel(gA, gA_or) <= 1e-3
 
 
+@pytest.mark.timeout(900)
 def test_adjoint_full_size_vs_oracle_and_fd(Solver, oracle):
     """The adjoint workload at full size: m=50k, n=100k, 8 nonzeros per
     column, K=200 steps, checkpoint every 20, loss ||x_K - x_t||^2."""
@@ -273,3 +274,50 @@ def test_tape_outliving_its_solver_is_released_cleanly(Solver, oracle):
     with pytest.raises(PDHGError):
         tape.backward(np.ones(lp.n))
     tape.free()
+
+
+def test_stale_tape_is_refused(Solver):
+    """A tape replays the context's current problem data: after a change of
+    values, right-hand side or objective, scaling or problem, its backward
+    pass is refused instead of mixing two problems."""
+    from paper_2510_24429_amd._lib import PDHGError
+    lp = lpgen.planted_uniform(m=100, n=200, k=4, seed=44)
+    other = lpgen.planted_uniform(m=60, n=150, k=3, seed=45)
+    g = np.linspace(-1.0, 1.0, lp.n)
+    with Solver.from_lp(lp) as s:
+        s.configure(ruiz_passes=10, power_iters=5)
+        _, tape = s.unrolled_forward(10, 5, 0.1, 0.1)
+        ref = tape.backward(g)
+        again = tape.backward(g)            # unchanged data: same result
+        for a, b in zip(ref, again):
+            assert np.array_equal(a, b)
+        tape.free()
+        changes = [lambda: s.set_values(lp.a_v * 1.5),
+                   lambda: s.set_rhs_obj(c=lp.c * 2.0),
+                   lambda: s.configure(ruiz_passes=10, power_iters=5)]
+        for change in changes:
+            s.set_values(lp.a_v)
+            s.set_rhs_obj(lp.b, lp.c)
+            s.configure(ruiz_passes=10, power_iters=5)
+            _, tape = s.unrolled_forward(10, 5, 0.1, 0.1)
+            change()
+            with pytest.raises(PDHGError, match="STATE"):
+                tape.backward(g)
+            tape.free()
+        # a reload with other sizes frees the tape's memory; the handle is
+        # refused and still released cleanly
+        s.set_values(lp.a_v)
+        s.set_rhs_obj(lp.b, lp.c)
+        s.configure(ruiz_passes=10, power_iters=5)
+        _, tape = s.unrolled_forward(10, 5, 0.1, 0.1)
+        s.load_lp(other)
+        with pytest.raises(PDHGError, match="STATE"):
+            tape.backward(np.ones(other.n))
+        tape.free()
+        # the reloaded context runs a fresh forward and backward
+        s.configure(ruiz_passes=10, power_iters=5)
+        _, tape = s.unrolled_forward(10, 5, 0.1, 0.1)
+        gc, gb, gA = tape.backward(np.ones(other.n))
+        assert gc.shape == (other.n,) and gb.shape == (other.m,)
+        assert np.isfinite(gA).all()
+        tape.free()
