@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the restarted PDHG hot path on one MI355X.
 
-Workload: the power-law LP m=200k, n=1M, nnz~9.4M (column counts ~ k^-2.1
-on [2, 5000], values N(0,1)*10^U(-2,2), planted optimum), FP64, Ruiz 10
-passes, target relative KKT 1e-8.  One step = one batch of eval_every (64)
-PDHG iterations (fused primal step + extrapolated dual step + averages) and
-its FP64 KKT evaluation with the restart / snapshot / stop decisions, i.e.
-every stage of the hot path.  value = PDHG iterations per second over the
-timed steps with all data resident in HBM.
+Headline workload: the largest single-GPU LP, m=5M, n=20M, nnz=110M (5
+nonzeros per column at random rows among the first m-50, plus 50 coupling
+rows of 200k entries; values N(0,1); planted optimum), FP64, Ruiz 10 passes,
+reflected Halpern iteration, target relative KKT 1e-8.  One step = one batch
+of eval_every (64) PDHG iterations (fused primal step + extrapolated dual
+step) and its FP64 KKT evaluation with the restart / snapshot / stop
+decisions, i.e. every stage of the hot path, replayed as one HIP graph.
+value = PDHG iterations per second over the timed steps, all data resident
+in HBM.
 
-Also reported (outside the timed region): per-kernel HIP-event durations
-and the algorithmic HBM bandwidth of the dominant kernel (roofline), the
-CPU oracle on a bounded sample (cpu_baseline), and the time to relative KKT
-1e-8 of the FP64 path and of FP32 bulk iterations with FP64 refinement.
+Also reported, outside the timed region:
+  - per-kernel HIP-event durations and the algorithmic HBM bandwidth of the
+    dominant kernel (roofline), its gather rate against the random-gather
+    ceiling measured live by the library's probe (pdhg_gather_probe);
+  - the averaged variant (PDLP-style restarts) and FP32 bulk steps on the
+    same LP;
+  - the CPU oracle on a bounded sample of the same LP (cpu_baseline);
+  - time to relative KKT 1e-8, FP64 vs FP32 bulk + FP64 refinement, on the
+    headline LP and on the power-law and multicommodity LPs, each run capped
+    so the whole benchmark fits its time budget (status and maxresid at the
+    cap are reported when 1e-8 is not reached);
+  - the multi-threaded CPU PDHG: iterations/s against the thread count.
 """
 from __future__ import annotations
 
@@ -28,24 +38,11 @@ sys.path.insert(0, ROOT)
 METRIC = ("PDHG iters/s + HBM GB/s; time to rel KKT 1e-8, FP32+refine vs "
           "FP64, 1 GPU")
 HBM_PEAK_GBS = 8000.0
-# Random 8-byte gathers per second on the MI355X by the size of the table each
-# XCD gathers from, measured by a probe of gathers alone (<= 2 MB ... >= 128 MB).
-GATHER_MB = (2, 4, 8, 16, 32, 128)
-GATHER_RATE = (195e9, 180e9, 110e9, 77e9, 63e9, 54e9)
+T_START = time.time()
 
 
-def gather_ceiling(table_bytes: float) -> float:
-    """Measured random-gather rate for a table of this size (log-log
-    interpolation between the probe's sizes)."""
-    import math
-    x = table_bytes / 1048576.0
-    if x <= GATHER_MB[0]:
-        return GATHER_RATE[0]
-    for i in range(1, len(GATHER_MB)):
-        if x <= GATHER_MB[i]:
-            f = math.log(x / GATHER_MB[i - 1]) / math.log(GATHER_MB[i] / GATHER_MB[i - 1])
-            return GATHER_RATE[i - 1] * (GATHER_RATE[i] / GATHER_RATE[i - 1]) ** f
-    return GATHER_RATE[-1]
+def log(msg: str):
+    print(f"[bench {time.time() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def alg_bytes(m: int, n: int, nnz: int, fp: int = 8, has_l: bool = False):
@@ -66,169 +63,6 @@ def alg_bytes(m: int, n: int, nnz: int, fp: int = 8, has_l: bool = False):
     return primal, dual
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="powerlaw_m200k_n1m")
-    ap.add_argument("--no-ttk", action="store_true", help="skip time-to-KKT runs")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle")
-    ap.add_argument("--ttk-cap", type=float, default=60.0,
-                    help="seconds allowed per time-to-KKT run")
-    ap.add_argument("--ttk-runs", type=int, default=3,
-                    help="time-to-KKT runs per path (median reported)")
-    ap.add_argument("--cpu-iters", type=int, default=64)
-    ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--variant", type=int, default=1,
-                    help="0: averaged iterates with PDLP-style restarts; "
-                         "1: reflected Halpern iteration (default)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one device copy of 256 MiB (reference for "
-                         "the profiler's byte counters)")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not "
-              "supported (the multi-GPU sharding is a design note only)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_2510_24429_amd import lpgen
-    from paper_2510_24429_amd.solver import Solver
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.copy_probe:
-        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    t0 = time.time()
-    lp = lpgen.make(args.workload)
-    print(f"[bench] generated {args.workload}: m={lp.m} n={lp.n} nnz={lp.nnz} "
-          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
-    N = 64
-    s = Solver.from_lp(lp, device=0)
-    s.configure(eps_rel=1e-8, eval_every=N, use_graph=0 if args.no_graph else 1,
-                variant=args.variant)
-    print(f"[bench] configured ({s.info()['t_setup']:.2f}s setup)",
-          file=sys.stderr, flush=True)
-
-    restarts_of_run = 0
-
-    def step():
-        nonlocal restarts_of_run
-        st = s.iterate(N)
-        if st != 0:        # converged inside the window: start over
-            restarts_of_run += 1
-            s.set_iterate(None, None)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    elapsed = tb - ta
-    iters = args.steps * N
-    value = iters / elapsed
-    print(f"[bench] timed {args.steps} steps: {elapsed:.3f}s, {value:.1f} iters/s",
-          file=sys.stderr, flush=True)
-
-    # per-kernel durations with HIP events on the library's stream
-    s.profile(True)
-    s.kernel_times(reset=True)
-    for _ in range(max(5, min(20, args.steps))):
-        step()
-    kt = s.kernel_times(reset=True)
-    s.profile(False)
-    bp, bd = alg_bytes(lp.m, lp.n, lp.nnz)
-    tp = kt["primal_step"]["total_ms"] / max(kt["primal_step"]["launches"], 1)
-    td = kt["dual_step"]["total_ms"] / max(kt["dual_step"]["launches"], 1)
-    gbs_p = bp / (tp * 1e-3) / 1e9
-    gbs_d = bd / (td * 1e-3) / 1e9
-    dominant = "primal_step" if tp >= td else "dual_step"
-    ach = gbs_p if dominant == "primal_step" else gbs_d
-    iter_gbs = (bp + bd) / ((tp + td) * 1e-3) / 1e9
-    print(f"[bench] primal {tp*1e3:.1f}us {gbs_p:.0f}GB/s  dual {td*1e3:.1f}us "
-          f"{gbs_d:.0f}GB/s  iteration {iter_gbs:.0f}GB/s", file=sys.stderr, flush=True)
-    # the same kernel against the measured random-gather rate for its table
-    # (y of m entries for the primal step, x of n for the dual step, each
-    # XCD holding 1/P of it when the side is panelled)
-    if dominant == "primal_step":
-        table = 8.0 * lp.m / s.panel_count(1)
-        t_dom = tp
-    else:
-        table = 8.0 * lp.n / s.panel_count(0)
-        t_dom = td
-    g_ach = lp.nnz / (t_dom * 1e-3)
-    g_cap = gather_ceiling(table)
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}.txt")
-    if os.path.exists(tfile):
-        tr = {}
-        with open(tfile) as f:
-            for line in f:
-                if not line.startswith("#") and ":" in line:
-                    k, v = line.split(":", 1)
-                    tr[k.strip()] = v.strip()
-        if tr.get("kernel_source_hash") == _kernel_hash():
-            traffic = int(tr["bytes_per_launch"])
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 2),
-        "unit": "iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded generator, planted optimum)",
-        "config": {"workload": args.workload, "m": lp.m, "n": lp.n,
-                   "nnz": lp.nnz, "precision": "fp64", "eval_every": N,
-                   "ruiz_passes": 10, "eps_rel": 1e-8,
-                   "variant": ["averaged", "halpern"][args.variant],
-                   "graphs": not args.no_graph},
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": dominant},
-        "kernels": {"primal_step": {"us": round(tp * 1e3, 2), "alg_bytes": bp,
-                                    "GB_s": round(gbs_p, 1)},
-                    "dual_step": {"us": round(td * 1e3, 2), "alg_bytes": bd,
-                                  "GB_s": round(gbs_d, 1)},
-                    "iteration_GB_s": round(iter_gbs, 1),
-                    "steps_only_iters_s": round(1e3 / (tp + td), 1),
-                    "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)},
-        "gather_rate": {"kernel": dominant, "achieved": round(g_ach / 1e9, 1),
-                        "ceiling": round(g_cap / 1e9, 1), "unit": "G gathers/s",
-                        "table_MB": round(table / 1048576.0, 2),
-                        "frac": round(g_ach / g_cap, 4)},
-        "restarts_of_run": restarts_of_run,
-    }
-
-    if not args.no_ttk:
-        out["time_to_kkt"] = time_to_kkt(Solver, lp, args.ttk_cap, args.variant,
-                                         args.ttk_runs)
-
-    s.close()
-
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, args.variant)
-        out["cpu_platform"] = cpu_platform(lp)
-
-    print(json.dumps(out), flush=True)
-
-
 def _kernel_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -239,62 +73,107 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_to_kkt(Solver, lp, cap, variant, runs):
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload, or None when it was taken on other sources."""
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(tfile):
+        return None
+    tr = {}
+    with open(tfile) as f:
+        for line in f:
+            if not line.startswith("#") and ":" in line:
+                k, v = line.split(":", 1)
+                tr[k.strip()] = v.strip()
+    if tr.get("kernel_source_hash") != _kernel_hash():
+        return None
+    return int(tr["bytes_per_launch"])
+
+
+def rate_and_kernels(s, lp, steps, warmup, N=64, fp=8, profile_steps=None):
+    """Time `steps` batches of N iterations after `warmup` (graphs), then the
+    per-kernel HIP-event durations of a few more batches."""
+    import torch
+    restarts = [0]
+
+    def step():
+        st = s.iterate(N)
+        if st != 0:        # converged inside the window: start over
+            restarts[0] += 1
+            s.set_iterate(None, None)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ta
+    s.profile(True)
+    s.kernel_times(reset=True)
+    for _ in range(profile_steps or max(3, min(10, steps))):
+        step()
+    kt = s.kernel_times(reset=True)
+    s.profile(False)
+    bp, bd = alg_bytes(lp.m, lp.n, lp.nnz, fp=fp)
+    tp = kt["primal_step"]["total_ms"] / max(kt["primal_step"]["launches"], 1)
+    td = kt["dual_step"]["total_ms"] / max(kt["dual_step"]["launches"], 1)
+    return dict(elapsed=elapsed, iters_s=steps * N / elapsed, tp=tp, td=td,
+                bp=bp, bd=bd, restarts=restarts[0],
+                gbs_p=bp / (tp * 1e-3) / 1e9, gbs_d=bd / (td * 1e-3) / 1e9,
+                iter_gbs=(bp + bd) / ((tp + td) * 1e-3) / 1e9)
+
+
+def kernels_dict(r):
+    return {"primal_step": {"us": round(r["tp"] * 1e3, 2), "alg_bytes": r["bp"],
+                            "GB_s": round(r["gbs_p"], 1)},
+            "dual_step": {"us": round(r["td"] * 1e3, 2), "alg_bytes": r["bd"],
+                          "GB_s": round(r["gbs_d"], 1)},
+            "iteration_GB_s": round(r["iter_gbs"], 1),
+            "steps_only_iters_s": round(1e3 / (r["tp"] + r["td"]), 1),
+            "iteration_frac": round(r["iter_gbs"] / HBM_PEAK_GBS, 4)}
+
+
+def time_to_kkt(s, lp, cap, variant, tag):
     """Wall time from data resident on the GPU (after load) to FP64 relative
-    KKT <= 1e-8: FP64 path vs FP32 bulk + FP64 refinement, `runs` runs each
-    (median reported; the runs are deterministic, so only the time varies)."""
+    KKT <= 1e-8, including Ruiz scaling and the power iteration: the FP64
+    path, then FP32 bulk iterations with FP64 refinement, on the loaded
+    context `s`, each within `cap` seconds."""
     import numpy as np
     import torch
-
-    def fp64():
-        with Solver.from_lp(lp, device=0) as s:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
-            st = s.solve()
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
-            inf = s.info()
-        print(f"[bench] ttk fp64: {t:.2f}s status {st} iters {inf['iters']} "
-              f"restarts {inf['restarts']} maxresid {inf['kkt']['maxresid']:.2e}",
-              file=sys.stderr, flush=True)
-        return {"seconds": t, "status": st, "iters": inf["iters"],
-                "restarts": inf["restarts"], "maxresid": inf["kkt"]["maxresid"],
-                "pobj": inf["kkt"]["pobj"]}
-
-    def fp32_refine():
-        with Solver.from_lp(lp, device=0) as s:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
-            r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=8,
-                                max_inner_iters=5_000_000)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
-        print(f"[bench] ttk fp32+refine: {t:.2f}s status {r['status']} rounds "
-              f"{r['rounds']} inner iters {r['inner_iters']} maxresid "
-              f"{r['kkt']['maxresid']:.2e}", file=sys.stderr, flush=True)
-        return {"seconds": t, "status": r["status"], "rounds": r["rounds"],
-                "inner_iters": r["inner_iters"], "maxresid": r["kkt"]["maxresid"],
-                "pobj": r["kkt"]["pobj"]}
-
     res = {}
-    for name, fn in (("fp64", fp64), ("fp32_refine", fp32_refine)):
-        rs = [fn()]
-        if rs[0]["seconds"] < 20.0:      # repeat only short runs
-            rs += [fn() for _ in range(runs - 1)]
-        ts = sorted(r["seconds"] for r in rs)
-        out = dict(rs[0])
-        out["seconds"] = round(ts[len(ts) // 2], 3)
-        out["runs_s"] = [round(r["seconds"], 3) for r in rs]
-        if any(r["status"] != rs[0]["status"] for r in rs):
-            out["status"] = [r["status"] for r in rs]
-        res[name] = out
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
+    st = s.solve()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    inf = s.info()
+    log(f"ttk {tag} fp64: {t:.2f}s status {st} iters {inf['iters']} restarts "
+        f"{inf['restarts']} maxresid {inf['kkt']['maxresid']:.2e}")
+    res["fp64"] = {"seconds": round(t, 3), "status": st, "cap_s": round(cap, 1),
+                   "iters": inf["iters"], "restarts": inf["restarts"],
+                   "maxresid": inf["kkt"]["maxresid"], "pobj": inf["kkt"]["pobj"]}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
+    r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=12,
+                        max_inner_iters=5_000_000)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    log(f"ttk {tag} fp32+refine: {t:.2f}s status {r['status']} rounds "
+        f"{r['rounds']} inner iters {r['inner_iters']} maxresid "
+        f"{r['kkt']['maxresid']:.2e}")
+    res["fp32_refine"] = {"seconds": round(t, 3), "status": r["status"],
+                          "cap_s": round(cap, 1), "rounds": r["rounds"],
+                          "inner_iters": r["inner_iters"],
+                          "maxresid": r["kkt"]["maxresid"], "pobj": r["kkt"]["pobj"]}
     if res["fp64"]["status"] == 1 and res["fp32_refine"]["status"] == 1:
         res["speedup_fp32_refine"] = round(res["fp64"]["seconds"] /
                                            res["fp32_refine"]["seconds"], 3)
-    # objective error of each result: against the planted optimum c^T x* when
-    # the generator planted one, and between the two paths
+    # objective error of each result: against the planted optimum c^T x*
+    # when the generator planted one, and between the two paths
     p64 = res["fp64"]["pobj"]
     if lp.x_star is not None:
         pstar = float(np.dot(lp.c, lp.x_star))
@@ -305,34 +184,44 @@ def time_to_kkt(Solver, lp, cap, variant, runs):
     return res
 
 
-def cpu_baseline(lp, iters, variant):
-    """The FP64 oracle, serial, on the same LP: `iters` iterations (with its
-    evaluations at k = 0 and every 64), setup (Ruiz, scaling) excluded."""
-    from oracle import oracle
-    t0 = time.time()
-    r = oracle.solve(lp, eps_rel=1e-8, max_iters=iters, eta=0.5, omega0=1.0,
-                     variant=variant)
-    wall = time.time() - t0
-    ips = r.info["iters"] / r.info["t_iter"]
-    print(f"[bench] cpu oracle: {r.info['iters']} iters in {r.info['t_iter']:.2f}s "
-          f"(setup {r.info['t_setup']:.2f}s, wall {wall:.1f}s)", file=sys.stderr,
-          flush=True)
-    model = ""
+def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": round(ips, 3), "unit": "iters/s", "cores": 1,
-            "kind": "oracle", "host_cpu": model, "host_cpus": os.cpu_count(),
-            "sample": f"{r.info['iters']} PDHG iterations of the same LP incl. "
-                      f"evaluations at k=0 and every 64, setup excluded, 1 thread"}
+    return ""
 
 
-def cpu_platform(lp, K: int = 8):
+def cpu_baseline(lp, iters, variant):
+    """The FP64 oracle, serial, on the same LP: `iters` iterations after its
+    evaluation at k = 0, timed by the difference of two runs (0 and `iters`
+    iterations), so the rate counts iterations alone.  Both runs skip Ruiz
+    scaling and the power iteration (fixed step and primal weight), whose
+    cost is setup, not iteration."""
+    from oracle import oracle
+    kw = dict(eps_rel=1e-8, eta=0.5, omega0=1.0, variant=variant, ruiz_passes=0,
+              eval_every=1 << 30)
+    t0 = time.time()
+    r0 = oracle.solve(lp, max_iters=0, **kw)
+    r1 = oracle.solve(lp, max_iters=iters, **kw)
+    wall = time.time() - t0
+    dt = r1.info["t_iter"] - r0.info["t_iter"]
+    ips = r1.info["iters"] / dt
+    log(f"cpu oracle: {r1.info['iters']} iters in {dt:.2f}s (evaluation "
+        f"{r0.info['t_iter']:.2f}s, wall {wall:.1f}s)")
+    return {"value": round(ips, 4), "unit": "iters/s", "cores": 1,
+            "kind": "oracle", "host_cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{r1.info['iters']} PDHG iterations (Halpern, FP64, serial "
+                      f"C oracle) of the same LP, timed as the difference of "
+                      f"runs of {iters} and 0 iterations so that the evaluation "
+                      f"at k=0 is excluded; Ruiz and power iteration skipped "
+                      f"(fixed step), 1 thread"}
+
+
+def cpu_platform(lp, budget_s):
     """The multi-threaded CPU step pair (no restarts or evaluations) on the
     same LP, iterations/s against the thread count, with its algorithmic
     bytes per iteration (CSR with 8-byte row pointers; the primal half reads
@@ -344,17 +233,213 @@ def cpu_platform(lp, K: int = 8):
                   + 32 * n + 24 * m)
     cap = os.cpu_count() or 1
     rows = []
-    t = 1
-    while t <= cap:
+    t, K = 1, 4
+    t_end = time.time() + budget_s
+    while t <= cap and time.time() < t_end:
         _, _, secs = cpu_steps(lp, np.zeros(n), np.zeros(m), 1e-3, 1e-3, K, t)
         ips = K / secs
         rows.append({"threads": t, "iters_s": round(ips, 2),
                      "GB_s": round(bytes_iter * ips / 1e9, 1)})
-        print(f"[bench] cpu steps, {t} threads: {ips:.1f} iters/s", file=sys.stderr,
-              flush=True)
-        t = t * 2 if t * 2 <= cap or t == cap else cap
+        log(f"cpu steps, {t} threads: {ips:.1f} iters/s")
+        if t == cap:
+            break
+        t = min(t * 2, cap)
     return {"kind": "cpu step pair", "steps_per_point": K, "bytes_per_iter": bytes_iter,
             "scaling": rows}
+
+
+def gather_sweep(Solver):
+    """The probe's random-gather rate by table size and panel count."""
+    from paper_2510_24429_amd import lpgen
+    lp = lpgen.make("uniform_m500_n1k")
+    s = Solver.from_lp(lp, device=0)
+    rows = []
+    for mb in (1, 2, 4, 8, 16, 32, 64, 128, 160):
+        ent = mb * 1048576 // 8
+        for P in (1, 2, 4, 8):
+            for nt in (0, 1):
+                g = s.gather_probe(ent, panels=P, stream_nt=nt, n_gathers=1 << 26, reps=5)
+                rows.append((mb, P, nt, g))
+                print(f"table {mb:4d} MB  panels {P}  per-XCD {mb / P:7.2f} MB  "
+                      f"stream_nt {nt}  {g / 1e9:7.1f} G gathers/s", flush=True)
+    s.close()
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="coupled_m5m_n20m")
+    ap.add_argument("--budget", type=float, default=480.0,
+                    help="seconds for the whole run: the time-to-KKT caps "
+                         "shrink to fit it")
+    ap.add_argument("--ttk-cap", type=float, default=150.0,
+                    help="largest cap per time-to-KKT run (seconds)")
+    ap.add_argument("--no-ttk", action="store_true", help="skip time-to-KKT runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline workload only (no variant / FP32 rates, no "
+                         "other workloads)")
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="oracle iterations for cpu_baseline (0: by size)")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--variant", type=int, default=1,
+                    help="0: averaged iterates with PDLP-style restarts; "
+                         "1: reflected Halpern iteration (default)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of 256 MiB (reference for "
+                         "the profiler's byte counters)")
+    ap.add_argument("--gather-sweep", action="store_true",
+                    help="print the probe's gather rates by table size and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the multi-GPU sharding is a design note only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_24429_amd import lpgen
+    from paper_2510_24429_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gather_sweep:
+        gather_sweep(Solver)
+        return
+    if args.copy_probe:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def left():
+        return args.budget - (time.time() - T_START)
+
+    t0 = time.time()
+    lp = lpgen.make(args.workload)
+    log(f"generated {args.workload}: m={lp.m} n={lp.n} nnz={lp.nnz} "
+        f"({time.time() - t0:.1f}s)")
+    N = 64
+    t0 = time.time()
+    s = Solver.from_lp(lp, device=0)
+    t_load = time.time() - t0
+    s.configure(eps_rel=1e-8, eval_every=N, use_graph=0 if args.no_graph else 1,
+                variant=args.variant)
+    log(f"loaded ({t_load:.1f}s), configured ({s.info()['t_setup']:.2f}s setup), "
+        f"panels A {s.panel_count(0)} A^T {s.panel_count(1)}")
+
+    r = rate_and_kernels(s, lp, args.steps, args.warmup, N)
+    value = r["iters_s"]
+    log(f"timed {args.steps} steps: {r['elapsed']:.3f}s, {value:.1f} iters/s; "
+        f"primal {r['tp']*1e3:.1f}us {r['gbs_p']:.0f}GB/s  dual {r['td']*1e3:.1f}us "
+        f"{r['gbs_d']:.0f}GB/s  iteration {r['iter_gbs']:.0f}GB/s")
+    dominant = "primal_step" if r["tp"] >= r["td"] else "dual_step"
+    ach = r["gbs_p"] if dominant == "primal_step" else r["gbs_d"]
+    # the same kernel's gathers (one per nonzero) against the probe's rate for
+    # the table it gathers from (y of m entries for the primal step, x of n
+    # for the dual step, each XCD holding 1/P of it when panelled)
+    if dominant == "primal_step":
+        cols, P, side = lp.m, s.panel_count(1), 1
+        t_dom = r["tp"]
+    else:
+        cols, P, side = lp.n, s.panel_count(0), 0
+        t_dom = r["td"]
+    table_xcd = 8.0 * cols / P
+    nt = 1 if table_xcd > 3 * 1048576 else 0     # the library's load-kind rule
+    g_cap = s.gather_probe(cols, panels=P, stream_nt=nt, n_gathers=lp.nnz, reps=3)
+    g_ach = lp.nnz / (t_dom * 1e-3)
+    log(f"{dominant}: {g_ach / 1e9:.1f} G gathers/s against the probe's "
+        f"{g_cap / 1e9:.1f} G/s ({table_xcd / 1048576:.1f} MB per XCD)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["elapsed"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator, planted optimum)",
+        "config": {"workload": args.workload, "m": lp.m, "n": lp.n,
+                   "nnz": lp.nnz, "precision": "fp64", "eval_every": N,
+                   "ruiz_passes": 10, "eps_rel": 1e-8,
+                   "variant": ["averaged", "halpern"][args.variant],
+                   "graphs": not args.no_graph,
+                   "panels": [s.panel_count(0), s.panel_count(1)]},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic(dominant, args.workload),
+                     "kernel": dominant},
+        "kernels": kernels_dict(r),
+        "gather_rate": {"kernel": dominant, "achieved": round(g_ach / 1e9, 1),
+                        "ceiling": round(g_cap / 1e9, 1), "unit": "G gathers/s",
+                        "ceiling_source": "pdhg_gather_probe, measured in this run",
+                        "table_MB_per_xcd": round(table_xcd / 1048576.0, 2),
+                        "frac": round(g_ach / g_cap, 4)},
+        "restarts_of_run": r["restarts"],
+    }
+
+    if not args.no_extra:
+        # the averaged variant and FP32 bulk steps on the same loaded LP
+        s.configure(eps_rel=1e-8, eval_every=N, variant=0)
+        r0 = rate_and_kernels(s, lp, max(5, args.steps // 2), 2, N)
+        log(f"averaged variant: {r0['iters_s']:.1f} iters/s, primal {r0['tp']*1e3:.1f}us "
+            f"dual {r0['td']*1e3:.1f}us")
+        out["averaged_variant"] = {"iters_s": round(r0["iters_s"], 2),
+                                   "kernels": kernels_dict(r0)}
+        s.configure(eps_rel=1e-8, eval_every=N, variant=args.variant, precision=1)
+        r32 = rate_and_kernels(s, lp, max(5, args.steps // 2), 2, N, fp=4)
+        log(f"fp32 steps: {r32['iters_s']:.1f} iters/s, primal {r32['tp']*1e3:.1f}us "
+            f"dual {r32['td']*1e3:.1f}us")
+        out["fp32_steps"] = {"iters_s": round(r32["iters_s"], 2),
+                             "kernels": kernels_dict(r32)}
+
+    if not args.no_cpu:
+        # about 12 s of serial iterations (the oracle runs ~3 s per iteration
+        # on 110M nonzeros), plus two evaluations at k = 0
+        iters = args.cpu_iters or max(2, min(64, int(0.45e9 / max(lp.nnz, 1))))
+        out["cpu_baseline"] = cpu_baseline(lp, iters, args.variant)
+
+    ttk = {}
+    if not args.no_extra:
+        # the power-law LP: the rate of round-one's headline, and both paths
+        # to 1e-8 (they finish in about 45 s and 15 s)
+        lp1 = lpgen.make("powerlaw_m200k_n1m")
+        with Solver.from_lp(lp1, device=0) as s1:
+            s1.configure(eps_rel=1e-8, eval_every=N, variant=args.variant)
+            r1 = rate_and_kernels(s1, lp1, 40, 5, N)
+            log(f"powerlaw_m200k_n1m: {r1['iters_s']:.1f} iters/s")
+            out["powerlaw_m200k_n1m"] = {"iters_s": round(r1["iters_s"], 2),
+                                         "kernels": kernels_dict(r1)}
+            if not args.no_ttk and left() > 150:
+                ttk["powerlaw_m200k_n1m"] = time_to_kkt(
+                    s1, lp1, min(args.ttk_cap, 90.0), args.variant, "powerlaw")
+        del lp1
+        if not args.no_cpu:
+            out["cpu_platform"] = cpu_platform(lp, min(30.0, max(left() - 300, 5.0)))
+        if not args.no_ttk and left() > 260:
+            lp2 = lpgen.make("mcf_150knodes_600karcs_k8")
+            with Solver.from_lp(lp2, device=0) as s2:
+                cap = min(args.ttk_cap, (left() - 120) / 2)
+                ttk["mcf_150knodes_600karcs_k8"] = time_to_kkt(
+                    s2, lp2, cap, args.variant, "multicommodity")
+            del lp2
+    if not args.no_ttk:
+        cap = min(args.ttk_cap, max(left() - 20, 20.0) / 2)
+        ttk[args.workload] = time_to_kkt(s, lp, cap, args.variant, "headline")
+        out["time_to_kkt"] = ttk
+    s.close()
+    log("done")
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
