@@ -32,6 +32,7 @@
 #ifndef PDHG_H
 #define PDHG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -534,6 +535,27 @@ int pdhg_cpu_stream_bw(int threads, int64_t bytes, int reps, double *gb_s);
  * values to float and accumulates in float; out is widened to double). */
 int pdhg_spmv(pdhg_ctx *ctx, int which, int scaled, int precision,
               const double *in, double *out, int mem);
+
+/* Allocation-free variant of pdhg_spmv, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * pdhg_spmv (bitwise); its staging vectors (input and output in the internal
+ * order, plus their FP32 copies for precision = PDHG_FP32) live in a
+ * library-owned device array of PDHG_SPMV_NOALLOC_MAX_BYTES bytes, one per
+ * GPU, held from library load until the process ends, instead of buffers
+ * allocated per call.  The call itself allocates nothing on the device or
+ * the host.  Staging needs 8 (rows + cols) bytes in FP64 and 12 (rows + cols)
+ * bytes in FP32 (each array rounded up to 256 bytes), rows x cols being the
+ * side's shape (A: m x n, A^T: n x m); larger problems get PDHG_E_ARG and a
+ * message.  Every context on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (from several threads, or on several streams)
+ * race and must be serialised by the caller.  The array keeps the last
+ * call's contents; nothing in it needs to start at zero.  With
+ * mem = PDHG_MEM_DEVICE the call issues only kernels and device-to-device
+ * copies on the context's stream, followed by a stream synchronisation. */
+#define PDHG_SPMV_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int pdhg_spmv_noalloc(pdhg_ctx *ctx, int which, int scaled, int precision,
+                      const double *in, double *out, int mem);
 
 /* Row-bin tuning, taking effect at the next pdhg_load:
  *  "split_threshold": nnz above which a row is split over several

@@ -19,6 +19,8 @@ STATUS = {0: "RUNNING", 1: "CONVERGED", 2: "ITER_LIMIT", 3: "TIME_LIMIT",
           4: "CANCELLED", 5: "NUMERICAL"}
 MEM_HOST, MEM_DEVICE = 0, 1
 FP64, FP32 = 0, 1
+# device scratch of pdhg_spmv_noalloc (PDHG_SPMV_NOALLOC_MAX_BYTES)
+SPMV_NOALLOC_MAX_BYTES = 64 << 20
 
 
 class PDHGError(RuntimeError):
@@ -157,6 +159,7 @@ SIGNATURES = {
     "pdhg_unrolled_backward": (i32, [vp, vp, vp, vp, vp, i32]),
     "pdhg_tape_free": (None, [vp]),
     "pdhg_spmv": (i32, [vp, i32, i32, i32, vp, vp, i32]),
+    "pdhg_spmv_noalloc": (i32, [vp, i32, i32, i32, vp, vp, i32]),
     "pdhg_gather_probe": (i32, [vp, i64, i32, i32, i32, i64, i32,
                                 C.POINTER(C.c_double)]),
     "pdhg_set_tuning": (i32, [vp, C.c_char_p, i64]),

@@ -82,9 +82,40 @@ struct CbItem {
 
 }  // namespace
 
+// Device scratch of the allocation-free SpMV (pdhg_spmv_noalloc): one copy per
+// GPU, held from module load until the process ends.  Host code never uses
+// this name as an address; it uses the per-device pointer that
+// hipGetSymbolAddress returns (scratch_ptr below).
+constexpr size_t kScratchBytes = PDHG_SPMV_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current.
+void *scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        throw DevError{PDHG_E_DEVICE, "device ordinal beyond the scratch table"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                  "hipGetSymbolAddress(scratch)");
+        if (!p) throw DevError{PDHG_E_DEVICE, "null scratch address"};
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 struct pdhg_ctx {
     int device = 0;
+    void *scratch = nullptr;    // this device's copy of `scratch` (device address)
     hipStream_t stream = nullptr, copy_stream = nullptr;
     bool own_stream = false;
     std::string err;
@@ -283,6 +314,15 @@ struct SpmvStage {
     double *din = nullptr, *dout = nullptr;
     float *i32 = nullptr, *o32 = nullptr;
 };
+
+// Bytes of SpmvStage for a side with `cols` inputs and `rows` outputs, each
+// array rounded up to 256 bytes.
+size_t spmv_noalloc_bytes(int64_t cols, int64_t rows, int precision) {
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t b = r((size_t)cols * 8) + r((size_t)rows * 8);
+    if (precision == PDHG_FP32) b += r((size_t)cols * 4) + r((size_t)rows * 4);
+    return b;
+}
 
 // FP32 values of M (and of its panel copy, whose FP64 values are rewritten
 // from the same source) rounded from `vals` (nnz, M's order).
@@ -1163,6 +1203,7 @@ int pdhg_create(int device, void *hip_stream, pdhg_ctx **out) {
         HIPC(hipGetDeviceCount(&count));
         if (device < 0 || device >= count) throw DevError{PDHG_E_ARG, "no such device"};
         HIPC(hipSetDevice(device));
+        c->scratch = scratch_ptr(device);
         if (hip_stream) {
             c->stream = (hipStream_t)hip_stream;
         } else {
@@ -1839,6 +1880,39 @@ int pdhg_spmv(pdhg_ctx *c, int which, int scaled, int precision,
         throw;
     }
     dfree(st.din), dfree(st.dout), dfree(st.i32), dfree(st.o32);
+    return PDHG_OK;
+    API_END(c)
+}
+
+int pdhg_spmv_noalloc(pdhg_ctx *c, int which, int scaled, int precision,
+                      const double *in, double *out, int mem) {
+    API_BEGIN(c)
+    if (!c->loaded) return fail(c, PDHG_E_STATE, "no problem loaded");
+    if (which < 0 || which > 1 || !in || !out) return fail(c, PDHG_E_ARG, "bad argument");
+    if (!c->scratch) return fail(c, PDHG_E_STATE, "no device scratch");
+    const DevCsr &M = which ? c->At : c->A;
+    const size_t need = spmv_noalloc_bytes(M.cols, M.rows, precision);
+    if (need > kScratchBytes)
+        return fail(c, PDHG_E_ARG,
+                    "pdhg_spmv_noalloc: staging of " + std::to_string(need) +
+                        " bytes exceeds the " + std::to_string(kScratchBytes) +
+                        "-byte device scratch (rows + cols too large)");
+    // carve the staging vectors out of the scratch, 256-byte aligned
+    unsigned char *base = (unsigned char *)c->scratch;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return (void *)p;
+    };
+    SpmvStage st;
+    st.din = (double *)take((size_t)M.cols * sizeof(double));
+    st.dout = (double *)take((size_t)M.rows * sizeof(double));
+    if (precision == PDHG_FP32) {
+        st.i32 = (float *)take((size_t)M.cols * sizeof(float));
+        st.o32 = (float *)take((size_t)M.rows * sizeof(float));
+    }
+    spmv_staged(c, which, scaled, precision, in, out, mem, st);
     return PDHG_OK;
     API_END(c)
 }

@@ -320,6 +320,36 @@ class Solver:
                                    po, mem), self.ctx)
         return out
 
+    def spmv_noalloc(self, which: int, vec, scaled: bool = False,
+                     precision: int = L.FP64, out=None):
+        """pdhg_spmv_noalloc: the same product with the library's fixed
+        device scratch as staging.  With a device `vec` and a device `out`
+        (torch tensors on this GPU) nothing is allocated anywhere."""
+        nin = self.n if which == 0 else self.m
+        nout = self.m if which == 0 else self.n
+        a = _Arg(vec, np.float64, nin, "vec")
+        if out is None:
+            out, po, mem = self._out(nout, a.mem == L.MEM_DEVICE)
+        else:
+            # written in place: must already be float64, contiguous, nout long
+            if _is_torch(out):
+                ok = (out.dtype == _torch().float64 and out.is_contiguous()
+                      and out.numel() == nout)
+                po = C.c_void_p(out.data_ptr())
+                mem = L.MEM_DEVICE if out.is_cuda else L.MEM_HOST
+            else:
+                ok = (isinstance(out, np.ndarray) and out.dtype == np.float64
+                      and out.flags.c_contiguous and out.flags.writeable
+                      and out.size == nout)
+                po, mem = (out.ctypes.data_as(C.c_void_p) if ok else None), L.MEM_HOST
+            if not ok:
+                raise ValueError(f"out: expected a contiguous float64 array of {nout}")
+            if mem != a.mem:
+                raise ValueError("vec and out must both be host or both device")
+        L.check(self.lib.pdhg_spmv_noalloc(self.ctx, which, int(scaled), precision,
+                                           a.ptr, po, mem), self.ctx)
+        return out
+
     def gather_probe(self, table_entries: int, precision: int = L.FP64,
                      panels: int = 1, stream_nt: int = 0,
                      n_gathers: int = 1 << 25, reps: int = 5) -> float:

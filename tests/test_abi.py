@@ -30,6 +30,13 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
 
 
+def test_noalloc_scratch_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define PDHG_SPMV_NOALLOC_MAX_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "PDHG_SPMV_NOALLOC_MAX_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == L.SPMV_NOALLOC_MAX_BYTES
+
+
 def test_struct_layouts_match_header(tmp_path):
     # compile a probe against the header and compare every field offset with
     # the ctypes mirror
