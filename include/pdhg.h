@@ -156,7 +156,8 @@ typedef struct {
     double inner_eps;           /* inner (correction LP) eps_rel (1e-4) */
     int32_t max_rounds;         /* refinement rounds after round 0 (8) */
     int32_t cap_log2;           /* scale growth cap per round, 2^cap (10) */
-    int64_t max_inner_iters;    /* per inner solve (200000) */
+    int64_t max_inner_iters;    /* iteration budget of a round's inner solve
+                                   (200000); see pdhg_solve_refined */
     double progress;            /* an inner solve also stops once the refined
                                    point's FP64 maxresid <= max(outer_eps,
                                    progress * maxresid before the round) (1e-2) */
@@ -165,6 +166,11 @@ typedef struct {
                                    final primal weight times
                                    (D_D/D_D,prev)/(D_P/D_P,prev); 0: from
                                    ||c^||/||b^|| of the correction LP (1) */
+    int64_t stall_iters;        /* a round ends early once the refined point
+                                   has not improved for max(stall_iters, 4 x
+                                   the iterations it took to reach its best)
+                                   inner iterations; 0: 65536 (the default),
+                                   < 0: never; see pdhg_solve_refined */
 } pdhg_refine_params;
 
 typedef struct {
@@ -230,7 +236,8 @@ int pdhg_plan_bins(int64_t rows, const int64_t *rp, int tile,
  * for a stream the context creates (default priority). */
 int pdhg_create(int device, void *hip_stream, pdhg_ctx **out);
 void pdhg_destroy(pdhg_ctx *ctx);
-/* Last error message of this context; valid until the next call on it. */
+/* Last error message of this context; valid until the next call on it.
+ * With ctx NULL: the message of this thread's last failed pdhg_create. */
 const char *pdhg_last_error(const pdhg_ctx *ctx);
 
 /* ---- problem data ------------------------------------------------------ */
@@ -410,10 +417,18 @@ int pdhg_concurrent_crossover_refined(pdhg_ctx *ctx, pdhg_crossover_fn fn,
  * LP  min (Delta_D d)^T xh  s.t.  A xh = Delta_P r_P,  xh >= -Delta_P x
  * with FP32 bulk iterations and FP64 evaluations, and updates in FP64
  * x <- max(0, x + xh / Delta_P), y <- y + yh / Delta_D, until the FP64
- * maxresid <= outer_eps.  An inner solve stops at inner_eps or when the
- * refined point has gained the factor `progress`; a round after the first
- * starts from the previous round's final primal weight rescaled by the change
- * of Delta_D / Delta_P.  Uses the parameters of the last configure (its
+ * maxresid <= outer_eps.  Each inner evaluation measures the refined point
+ * in FP64 and keeps the best one.  An inner solve stops at inner_eps, when
+ * the refined point has gained the factor `progress`, when it has not
+ * improved for max(stall_iters, 4 x the iterations to its best), or at its
+ * budget of max_inner_iters; a budget or stall end before any improvement
+ * extends the same solve, doubling budget and stall window, up to 16 times
+ * max_inner_iters.  The round then takes its best refined point (or the
+ * final one, if better) when that improves on the maxresid before the round:
+ * partial progress is kept.  A round that cannot improve ends the refinement
+ * (status PDHG_ITER_LIMIT).  A round after the first starts from the previous
+ * round's final primal weight rescaled by the change of Delta_D / Delta_P.
+ * Uses the parameters of the last configure (its
  * precision field is ignored; its time_limit_s bounds the whole
  * refinement).  The configured snapshot levels apply to the refined iterate:
  * its FP64 maxresid is measured before every round and at the end, and
@@ -423,10 +438,11 @@ int pdhg_concurrent_crossover_refined(pdhg_ctx *ctx, pdhg_crossover_fn fn,
 int pdhg_solve_refined(pdhg_ctx *ctx, const pdhg_refine_params *rp,
                        pdhg_refine_info *info);
 
-/* Per-round log of the last pdhg_solve_refined: up to cap records of 8
+/* Per-round log of the last pdhg_solve_refined: up to cap records of 10
  * doubles (round, FP64 maxresid of the outer iterate before the round,
  * Delta_P, Delta_D, inner iterations, inner status, inner maxresid, seconds
- * since the start); *count gets the number of records. */
+ * since the start, 1 if the round was ended early for stalling, 1 if its
+ * refined point was accepted); *count gets the number of records. */
 int pdhg_refine_log(pdhg_ctx *ctx, double *out, int cap, int *count);
 
 /* ---- unrolled steps and their adjoint ------------------------------------ */

@@ -89,7 +89,8 @@ class RefineParams(C.Structure):
     _fields_ = [("outer_eps", C.c_double), ("inner_eps", C.c_double),
                 ("max_rounds", C.c_int32), ("cap_log2", C.c_int32),
                 ("max_inner_iters", C.c_int64), ("progress", C.c_double),
-                ("inner_precision", C.c_int32), ("omega_carry", C.c_int32)]
+                ("inner_precision", C.c_int32), ("omega_carry", C.c_int32),
+                ("stall_iters", C.c_int64)]
 
 
 class RefineInfo(C.Structure):
@@ -196,6 +197,15 @@ def lib():
     """Load libpdhg.so (built in-tree by __graft_entry__.build())."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as the
+        # system one this library links; loading torch first makes the
+        # library bind to that runtime, so torch's tensors and streams and
+        # the library share one (loaded the other way round, the system
+        # runtime has been seen to find no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
@@ -210,12 +220,22 @@ def lib():
 
 
 def check(rc: int, ctx=None):
+    """Raise PDHGError for a negative return code, with the context's
+    message when there is a context."""
     if rc < 0:
         msg = ""
         if ctx:
             m = lib().pdhg_last_error(ctx)
             msg = m.decode() if m else ""
         raise PDHGError(rc, msg)
+    return rc
+
+
+def check_create(rc: int):
+    """check() for pdhg_create: the message of this thread's failed create."""
+    if rc < 0:
+        m = lib().pdhg_last_error(None)
+        raise PDHGError(rc, m.decode() if m else "")
     return rc
 
 

@@ -195,10 +195,17 @@ struct pdhg_ctx {
     bool keep_snaps = false;        // refinement: inner solves keep the list
     bool keep_cancel = false;       // refinement: inner solves keep a cancel
     std::function<void(int)> snap_hook;   // new snapshots [arg, end) recorded
-    std::vector<double> refine_log;   // 8 doubles per refinement round
-    // outer-progress test of a refinement inner solve (active when set)
+    std::vector<double> refine_log;   // 10 doubles per refinement round
+    // outer-progress test of a refinement inner solve (active when set):
+    // the round's outer iterate, scales and target; the best refined point
+    // its evaluations have seen (FP64, scaled), its maxresid and iteration;
+    // the stall window and whether the round was ended for stalling
     const double *ref_xo = nullptr, *ref_yo = nullptr;
     double ref_DP = 1.0, ref_DD = 1.0, ref_target = -1.0;
+    double *ref_bx = nullptr, *ref_by = nullptr;
+    double ref_best = INFINITY;
+    int64_t ref_best_k = 0, ref_stall = 0;
+    bool ref_cut = false;
 
     // callback thread
     pdhg_snapshot_cb cb = nullptr;
@@ -448,6 +455,8 @@ void free_problem(pdhg_ctx *c) {
     dfree(c->lh32);
     dfree(c->xo);
     dfree(c->yo);
+    dfree(c->ref_bx);
+    dfree(c->ref_by);
     for (double **p : {&c->pol_x, &c->pol_y, &c->pol_xp, &c->pol_yd, &c->zero_n, &c->zero_m})
         dfree(*p);
     dfree(c->zero_n32);
@@ -1015,6 +1024,13 @@ bool refine_outer_reached_T(pdhg_ctx *c, Iter<T> &v) {
     launch_refine_update<T>(c->xo, c->yo, xi, yi, ls, c->ref_DP, c->ref_DD, c->m, c->n, c->stream);
     pdhg_kkt K;
     kkt_pair64(c, c->xo, c->yo, c->bs, c->cs, ls, c->nb, c->nc, &K);
+    if (K.maxresid < c->ref_best) {
+        // the best refined point of the round so far
+        HIPC(hipMemcpyAsync(c->ref_bx, c->xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPC(hipMemcpyAsync(c->ref_by, c->yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        c->ref_best = K.maxresid;
+        c->ref_best_k = c->k_host;
+    }
     const bool ok = K.maxresid <= c->ref_target;
     if (ok && th) {
         HIPC(hipMemcpyAsync(v.x, v.xbar, c->n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
@@ -1073,11 +1089,19 @@ int run_iterations(pdhg_ctx *c, int64_t max_more, int64_t limit_total) {
             c->k_host = c->st_host->k;
             collect_snapshots(c);
             if (c->status == PDHG_RUNNING && c->st_host->polish_due) polish(c);
-            if (c->status == PDHG_RUNNING && c->ref_target >= 0.0 &&
-                refine_outer_reached(c)) {
-                launch_set_status(c->st, PDHG_CONVERGED, c->stream);
-                read_state(c);
-                c->status = c->st_host->status;
+            if (c->status == PDHG_RUNNING && c->ref_target >= 0.0) {
+                if (refine_outer_reached(c)) {
+                    launch_set_status(c->st, PDHG_CONVERGED, c->stream);
+                    read_state(c);
+                    c->status = c->st_host->status;
+                } else if (c->ref_stall > 0 &&
+                           c->k_host - c->ref_best_k > std::max(c->ref_stall, 4 * c->ref_best_k)) {
+                    // the refined point has stopped improving: end the round
+                    c->ref_cut = true;
+                    launch_set_status(c->st, PDHG_ITER_LIMIT, c->stream);
+                    read_state(c);
+                    c->status = c->st_host->status;
+                }
             }
             if (c->status == PDHG_RUNNING) {
                 int stop = 0;
@@ -1184,17 +1208,26 @@ void configure_solve_state(pdhg_ctx *c) {
 
 extern "C" {
 
+// Message of the last failed pdhg_create on this thread (there is no
+// context to hold it).
+static thread_local std::string g_create_err;
+
 const char *pdhg_last_error(const pdhg_ctx *ctx) {
-    return ctx ? ctx->err.c_str() : "null context";
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
 
 int pdhg_create(int device, void *hip_stream, pdhg_ctx **out) {
-    if (!out) return PDHG_E_ARG;
+    g_create_err.clear();
+    if (!out) {
+        g_create_err = "null out pointer";
+        return PDHG_E_ARG;
+    }
     *out = nullptr;
     pdhg_ctx *c = nullptr;
     try {
         c = new pdhg_ctx();
     } catch (...) {
+        g_create_err = "host allocation failed";
         return PDHG_E_OOM;
     }
     c->device = device;
@@ -1216,10 +1249,12 @@ int pdhg_create(int device, void *hip_stream, pdhg_ctx **out) {
         HIPC(hipHostMalloc((void **)&c->st_host, sizeof(State), hipHostMallocDefault));
         std::memset(c->st_host, 0, sizeof(State));
         c->st = dmalloc<State>(1);
-    } catch (const DevError &) {
+    } catch (const DevError &e) {
+        g_create_err = e.msg;
         pdhg_destroy(c);
-        return PDHG_E_DEVICE;
+        return e.code == PDHG_E_ARG ? PDHG_E_ARG : PDHG_E_DEVICE;
     } catch (...) {
+        g_create_err = "host allocation failed";
         pdhg_destroy(c);
         return PDHG_E_OOM;
     }
@@ -2201,10 +2236,18 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
     double *xo = dmalloc<double>(c->n), *yo = dmalloc<double>(c->m);
     launch_fill(xo, 0.0, c->n, c->stream);
     launch_fill(yo, 0.0, c->m, c->stream);
+    if (!c->ref_bx) {
+        c->ref_bx = dmalloc<double>(c->n);
+        c->ref_by = dmalloc<double>(c->m);
+    }
     const pdhg_params saved = c->params;
     const std::vector<double> saved_levels = c->levels;
     const int saved_slots = c->n_slots;
-    double DP = 1.0, DD = 1.0, DPprev = 1.0, DDprev = 1.0, omega_end = 0.0;
+    double DP = 1.0, DD = 1.0;
+    // primal weight at the end of the last round whose inner solve converged,
+    // with that round's scales (a round cut at its budget or for a stall may
+    // end with a weight far off the correction LP's)
+    double omega_ref = 0.0, DP_ref = 1.0, DD_ref = 1.0;
     int status = PDHG_ITER_LIMIT, r = 0;
     int64_t inner_total = 0;
     pdhg_kkt K;
@@ -2256,7 +2299,7 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
             kkt_pair64(c, xo, yo, c->bs, c->cs, c->has_l ? c->ls : nullptr, c->nb, c->nc, &K);
             if (r > 0 && !c->refine_log.empty()) {
                 // close the previous round's record with the resulting KKT
-                c->refine_log[c->refine_log.size() - 8 + 7] = now_s() - t0;
+                c->refine_log[c->refine_log.size() - 10 + 7] = now_s() - t0;
             }
             snapshot_refined(K);
             if (K.maxresid <= R.outer_eps) {
@@ -2287,8 +2330,6 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
                 double d2[2];
                 HIPC(hipMemcpyAsync(d2, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
                 sync(c);
-                DPprev = DP;
-                DDprev = DD;
                 const double capP = std::ldexp(DP, R.cap_log2), capD = std::ldexp(DD, R.cap_log2);
                 auto pow2floor_inv = [](double d) {
                     int e = 0;
@@ -2311,8 +2352,8 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
             const double nch = std::sqrt(read_scalar(c, c->scal));
             const double nbs = dev_norm(c, c->bh, c->m), ncs = dev_norm(c, c->ch, c->n);
             double om = (nbs > 1e-10 && ncs > 1e-10) ? ncs / nbs : 1.0;
-            if (R.omega_carry && r >= 1 && omega_end > 0.0)
-                om = omega_end * (DD / DDprev) / (DP / DPprev);
+            if (R.omega_carry && r >= 1 && omega_ref > 0.0)
+                om = omega_ref * (DD / DD_ref) / (DP / DP_ref);
             // inner solve of the correction LP (FP32 bulk iterations unless
             // FP64 inner solves were asked for)
             c->act_bs = c->bh;
@@ -2341,20 +2382,66 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
             c->ref_DP = DP;
             c->ref_DD = DD;
             c->ref_target = std::max(R.outer_eps, R.progress * K.maxresid);
-            run_iterations(c, R.max_inner_iters, R.max_inner_iters);
+            c->ref_best = INFINITY;
+            c->ref_best_k = 0;
+            c->ref_cut = false;
+            // the inner solve runs to its target, its inner tolerance, a
+            // stall of the refined point (stall window: 0 means 65536
+            // iterations, < 0 none) or its budget.  A budget or stall end
+            // without any improvement of the refined point extends the same
+            // solve: budget and window double, up to 16 times the budget
+            c->ref_stall = R.stall_iters < 0 ? 0 : (R.stall_iters ? R.stall_iters : 65536);
+            int64_t budget = R.max_inner_iters;
+            for (;;) {
+                run_iterations(c, budget - c->k_host, budget);
+                if (c->status != PDHG_ITER_LIMIT || c->ref_best < K.maxresid ||
+                    budget >= (R.max_inner_iters << 4) || c->cancel_flag.load())
+                    break;
+                budget *= 2;
+                c->ref_stall *= 2;
+                c->ref_cut = false;
+                read_state(c);
+                c->st_host->status = PDHG_RUNNING;
+                write_state(c, *c->st_host);
+                c->status = PDHG_RUNNING;
+            }
             c->ref_target = -1.0;
-            omega_end = c->st_host->omega;
+            if (c->status == PDHG_CONVERGED) {
+                omega_ref = c->st_host->omega;
+                DP_ref = DP;
+                DD_ref = DD;
+            }
             inner_total += c->k_host;
             pdhg_kkt ik;
             kkt_of(c, 0, &ik);
-            const double rec[8] = {(double)r, K.maxresid, DP, DD,
-                                   (double)c->k_host, (double)c->status,
-                                   ik.maxresid, now_s() - t0};
-            c->refine_log.insert(c->refine_log.end(), rec, rec + 8);
+            // the round's refined point: the best its evaluations saw, or
+            // the final inner iterate's when that is better; kept only if it
+            // improves on the point before the round
+            HIPC(hipMemcpyAsync(c->xo, xo, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            HIPC(hipMemcpyAsync(c->yo, yo, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
             if (in64)
-                launch_refine_update<double>(xo, yo, c->v64.x, c->v64.y, ls, DP, DD, c->m, c->n, c->stream);
+                launch_refine_update<double>(c->xo, c->yo, c->v64.x, c->v64.y, ls, DP, DD, c->m, c->n, c->stream);
             else
-                launch_refine_update<float>(xo, yo, c->v32.x, c->v32.y, ls, DP, DD, c->m, c->n, c->stream);
+                launch_refine_update<float>(c->xo, c->yo, c->v32.x, c->v32.y, ls, DP, DD, c->m, c->n, c->stream);
+            pdhg_kkt KF;
+            kkt_pair64(c, c->xo, c->yo, c->bs, c->cs, ls, c->nb, c->nc, &KF);
+            const bool final_best = KF.maxresid <= c->ref_best;
+            const double after = final_best ? KF.maxresid : c->ref_best;
+            const bool accept = after < K.maxresid;
+            if (accept) {
+                const double *sx = final_best ? c->xo : c->ref_bx;
+                const double *sy = final_best ? c->yo : c->ref_by;
+                HIPC(hipMemcpyAsync(xo, sx, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                HIPC(hipMemcpyAsync(yo, sy, c->m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            }
+            const double rec[10] = {(double)r, K.maxresid, DP, DD,
+                                    (double)c->k_host, (double)c->status,
+                                    ik.maxresid, now_s() - t0,
+                                    c->ref_cut ? 1.0 : 0.0, accept ? 1.0 : 0.0};
+            c->refine_log.insert(c->refine_log.end(), rec, rec + 10);
+            // a round that could not improve the point even with its
+            // extensions would be repeated as it was: stop
+            if (!accept) break;
         }
     } catch (...) {
         c->ref_target = -1.0;
@@ -2426,11 +2513,11 @@ int pdhg_solve_refined(pdhg_ctx *c, const pdhg_refine_params *rp,
 
 int pdhg_refine_log(pdhg_ctx *c, double *out, int cap, int *count) {
     if (!c) return PDHG_E_ARG;
-    const int k = (int)(c->refine_log.size() / 8);
+    const int k = (int)(c->refine_log.size() / 10);
     if (count) *count = k;
     if (out)
         for (int i = 0; i < k && i < cap; ++i)
-            std::memcpy(out + 8 * i, c->refine_log.data() + 8 * i, 8 * sizeof(double));
+            std::memcpy(out + 10 * i, c->refine_log.data() + 10 * i, 10 * sizeof(double));
     return PDHG_OK;
 }
 

@@ -78,7 +78,7 @@ class Solver:
                 stream = C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
         self.device = device
         ctx = C.c_void_p()
-        L.check(self.lib.pdhg_create(device, stream, C.byref(ctx)))
+        L.check_create(self.lib.pdhg_create(device, stream, C.byref(ctx)))
         self.ctx = ctx
         self._keep = None
         self._cb = None
@@ -303,8 +303,9 @@ class Solver:
 
     def refine_log(self, cap: int = 64) -> np.ndarray:
         """Rows: round, outer maxresid before it, Delta_P, Delta_D, inner
-        iterations, inner status, inner maxresid, seconds since start."""
-        buf = np.zeros((cap, 8))
+        iterations, inner status, inner maxresid, seconds since start, ended
+        early for stalling (1/0), refined point accepted (1/0)."""
+        buf = np.zeros((cap, 10))
         cnt = C.c_int(0)
         L.check(self.lib.pdhg_refine_log(self.ctx, buf.ctypes.data_as(C.c_void_p),
                                          cap, C.byref(cnt)), self.ctx)

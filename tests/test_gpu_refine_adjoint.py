@@ -39,7 +39,8 @@ def test_fp32_refinement_reaches_1e8(Solver, oracle, name, variant):
                             max_inner_iters=50000)
         for row in s.refine_log():
             print("refine round %d outer %.3e DP %.3g DD %.3g inner iters %d "
-                  "status %d inner %.3e t %.2fs" % tuple(row), flush=True)
+                  "status %d inner %.3e t %.2fs cut %d accepted %d" % tuple(row),
+                  flush=True)
         assert r["status"] == 1, r
         assert r["rounds"] >= 1
         x, y, z = s.get_iterate()
@@ -62,6 +63,50 @@ def test_fp32_refinement_reaches_1e8(Solver, oracle, name, variant):
     assert err <= bound(kk) + bound(ref.kkt), (err, bound(kk), bound(ref.kkt))
 
 
+def test_refinement_cut_rounds_keep_partial_progress(Solver, oracle):
+    """Rounds bounded to 3000 inner iterations (the multicommodity LP's
+    rounds need up to ~38k): a round cut at its budget keeps the best refined
+    point it reached; one that has not improved yet is extended (6000,
+    12000, ...); the outer maxresid before each round falls, and the
+    refinement still reaches 1e-8, recomputed on the CPU."""
+    lp = lpgen.multicommodity(nodes=1500, arcs=6000, commodities=4, seed=2)
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-8, variant=1)
+        r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=60,
+                            max_inner_iters=3000)
+        log = s.refine_log()
+        for row in log:
+            print("refine round %d outer %.3e DP %.3g DD %.3g inner iters %d "
+                  "status %d inner %.3e t %.2fs cut %d accepted %d" % tuple(row),
+                  flush=True)
+        x, y, _ = s.get_iterate()
+    assert r["status"] == 1, r
+    cut = log[log[:, 5] == 2]                  # rounds ended at their budget
+    assert len(cut) >= 1
+    assert set(cut[:, 4].astype(int)) <= {3000 << k for k in range(5)}
+    assert np.all(cut[:, 9] == 1)              # ... whose progress was kept
+    assert np.all(log[:, 9] == 1)              # every round improved the point
+    assert np.all(np.diff(log[:, 1]) < 0)
+    kk = oracle.kkt(lp, x, y)
+    assert kk["maxresid"] <= 1e-8
+
+
+def test_refinement_stall_window_ends_rounds(Solver):
+    """A stall window of 64 iterations ends a round once its refined point
+    has not improved for max(64, 4 x the iterations to its best); rounds
+    ended that way keep their best point, and the refinement converges."""
+    lp = lpgen.multicommodity(nodes=1500, arcs=6000, commodities=4, seed=2)
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-8, variant=1)
+        r = s.solve_refined(outer_eps=1e-8, max_rounds=60, max_inner_iters=200000,
+                            stall_iters=64)
+        log = s.refine_log()
+    assert r["status"] == 1, r
+    assert np.all(np.diff(log[:, 1]) < 0)
+    # a cut is recorded as ITER_LIMIT with the stall flag set
+    assert np.all(log[log[:, 8] == 1][:, 5] == 2)
+
+
 @pytest.mark.parametrize("inner", [1, 0])
 def test_refinement_with_lower_bounds(Solver, oracle, inner):
     # x >= l with l < 0: the correction LP's bound is Delta_P (l - x) and the
@@ -76,7 +121,8 @@ def test_refinement_with_lower_bounds(Solver, oracle, inner):
                             max_inner_iters=50000)
         for row in s.refine_log():
             print("refine round %d outer %.3e DP %.3g DD %.3g inner iters %d "
-                  "status %d inner %.3e t %.2fs" % tuple(row), flush=True)
+                  "status %d inner %.3e t %.2fs cut %d accepted %d" % tuple(row),
+                  flush=True)
         assert r["status"] == 1, r
         x, y, _ = s.get_iterate()
     kk = oracle.kkt(lp, x, y, l=l)
