@@ -2440,8 +2440,15 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
                                     c->ref_cut ? 1.0 : 0.0, accept ? 1.0 : 0.0};
             c->refine_log.insert(c->refine_log.end(), rec, rec + 10);
             // a round that could not improve the point even with its
-            // extensions would be repeated as it was: stop
-            if (!accept) break;
+            // extensions would be repeated as it was: stop, reporting why the
+            // inner solve ended when it was stopped from outside
+            if (!accept) {
+                status = c->cancel_flag.load() ? PDHG_CANCELLED
+                         : c->status == PDHG_TIME_LIMIT ? PDHG_TIME_LIMIT
+                         : c->status == PDHG_NUMERICAL ? PDHG_NUMERICAL
+                                                       : PDHG_ITER_LIMIT;
+                break;
+            }
         }
     } catch (...) {
         c->ref_target = -1.0;
