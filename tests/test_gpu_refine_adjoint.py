@@ -91,20 +91,52 @@ def test_refinement_cut_rounds_keep_partial_progress(Solver, oracle):
     assert kk["maxresid"] <= 1e-8
 
 
-def test_refinement_stall_window_ends_rounds(Solver):
+def test_refinement_stall_window_cuts_rounds_and_keeps_best(Solver, oracle):
     """A stall window of 64 iterations ends a round once its refined point
-    has not improved for max(64, 4 x the iterations to its best); rounds
-    ended that way keep their best point, and the refinement converges."""
+    has not improved for max(64, 4 x the iterations to its best).  Rounds
+    ended that way keep their best point; a round that cannot improve even
+    with its window doubled four times ends the refinement with ITER_LIMIT,
+    keeping the point before it.  A fresh PDHG solve of a correction LP can
+    take thousands of iterations to gain, so such a short window may stop
+    short of the target where no window converges."""
     lp = lpgen.multicommodity(nodes=1500, arcs=6000, commodities=4, seed=2)
-    with Solver.from_lp(lp) as s:
-        s.configure(eps_rel=1e-8, variant=1)
-        r = s.solve_refined(outer_eps=1e-8, max_rounds=60, max_inner_iters=200000,
-                            stall_iters=64)
-        log = s.refine_log()
-    assert r["status"] == 1, r
-    assert np.all(np.diff(log[:, 1]) < 0)
+
+    def run(stall):
+        with Solver.from_lp(lp) as s:
+            s.configure(eps_rel=1e-8, variant=1)
+            r = s.solve_refined(outer_eps=1e-8, max_rounds=60, max_inner_iters=200000,
+                                stall_iters=stall)
+            log = s.refine_log()
+            x, y, _ = s.get_iterate()
+        for row in log:
+            print("stall %d refine round %d outer %.3e DP %.3g DD %.3g inner iters %d "
+                  "status %d inner %.3e t %.2fs cut %d accepted %d" % ((stall,) + tuple(row)),
+                  flush=True)
+        return r, log, oracle.kkt(lp, x, y)
+
+    r, log, kk = run(64)
+    assert r["status"] in (1, 2), r
+    cut = log[:, 8] == 1
+    assert cut.any()
     # a cut is recorded as ITER_LIMIT with the stall flag set
-    assert np.all(log[log[:, 8] == 1][:, 5] == 2)
+    assert np.all(log[cut][:, 5] == 2)
+    # every accepted round improved the point the next round starts from
+    acc = log[:, 9] == 1
+    assert np.all(acc[:-1])
+    assert np.all(np.diff(log[:, 1]) < 0)
+    if r["status"] == 2:
+        # the last round could not improve: the point before it is kept
+        assert not acc[-1]
+        assert r["kkt"]["maxresid"] == log[-1, 1]
+    else:
+        assert r["kkt"]["maxresid"] <= 1e-8
+    assert abs(kk["maxresid"] - r["kkt"]["maxresid"]) <= 1e-12 + 1e-9 * r["kkt"]["maxresid"]
+
+    # without a stall window the same refinement converges, no round cut
+    r, log, kk = run(-1)
+    assert r["status"] == 1, r
+    assert not (log[:, 8] == 1).any()
+    assert kk["maxresid"] <= 1e-8
 
 
 @pytest.mark.parametrize("inner", [1, 0])
