@@ -432,7 +432,7 @@ def main():
 
     ttk = {}
     if not args.no_extra:
-        # the power-law LP: the rate of round-one's headline, and both paths
+        # the power-law LP (m = 200k, n = 1M): its rate, and both paths
         # to 1e-8 (they finish in about 45 s and 15 s)
         lp1 = lpgen.make("powerlaw_m200k_n1m")
         with Solver.from_lp(lp1, device=0) as s1:
