@@ -214,7 +214,8 @@ def cpu_baseline(lp, iters, variant):
         f"{r0.info['t_iter']:.2f}s, wall {wall:.1f}s)")
     return {"value": round(ips, 4), "unit": "iters/s", "cores": 1,
             "kind": "oracle", "host_cpu": cpu_model(), "host_cpus": os.cpu_count(),
-            "sample": f"{r1.info['iters']} PDHG iterations (Halpern, FP64, serial "
+            "sample": f"{r1.info['iters']} PDHG iterations "
+                      f"({['averaged', 'Halpern'][variant]}, FP64, serial "
                       f"C oracle) of the same LP, timed as the difference of "
                       f"runs of {iters} and 0 iterations so that the evaluation "
                       f"at k=0 is excluded; Ruiz and power iteration skipped "
@@ -425,9 +426,9 @@ def main():
                              "kernels": kernels_dict(r32)}
 
     if not args.no_cpu:
-        # about 12 s of serial iterations (the oracle runs ~3 s per iteration
-        # on 110M nonzeros), plus two evaluations at k = 0
-        iters = args.cpu_iters or max(2, min(64, int(0.45e9 / max(lp.nnz, 1))))
+        # about 15 s of serial iterations (the oracle runs 1.0-1.5 s per
+        # iteration on 110M nonzeros), plus two evaluations at k = 0
+        iters = args.cpu_iters or max(2, min(64, int(1.4e9 / max(lp.nnz, 1))))
         out["cpu_baseline"] = cpu_baseline(lp, iters, args.variant)
 
     ttk = {}
