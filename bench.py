@@ -135,17 +135,34 @@ def kernels_dict(r):
             "iteration_frac": round(r["iter_gbs"] / HBM_PEAK_GBS, 4)}
 
 
+TTK_LEVELS = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+
+
+def _level_times(s):
+    """Seconds from the start of the iterations (after Ruiz and the power
+    iteration) and iterations to the first snapshot at each level.  The
+    refinement measures its refined point before every round and at the end,
+    so its times are those of the round boundaries."""
+    out = {}
+    for i in range(s.snapshot_count()):
+        inf = s.snapshot_info(i)
+        out[f"{inf['level']:.0e}"] = {"t_s": round(inf["t_wall"], 3), "iters": inf["iter"]}
+    return out
+
+
 def time_to_kkt(s, lp, cap, variant, tag):
     """Wall time from data resident on the GPU (after load) to FP64 relative
     KKT <= 1e-8, including Ruiz scaling and the power iteration: the FP64
     path, then FP32 bulk iterations with FP64 refinement, on the loaded
-    context `s`, each within `cap` seconds."""
+    context `s`, each within `cap` seconds.  Each path also reports when it
+    first reached the levels 1e-2 .. 1e-6 (snapshots), which compares the
+    two paths on an LP that neither finishes within the cap."""
     import numpy as np
     import torch
     res = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
+    s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant, levels=TTK_LEVELS)
     st = s.solve()
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -154,10 +171,11 @@ def time_to_kkt(s, lp, cap, variant, tag):
         f"{inf['restarts']} maxresid {inf['kkt']['maxresid']:.2e}")
     res["fp64"] = {"seconds": round(t, 3), "status": st, "cap_s": round(cap, 1),
                    "iters": inf["iters"], "restarts": inf["restarts"],
-                   "maxresid": inf["kkt"]["maxresid"], "pobj": inf["kkt"]["pobj"]}
+                   "maxresid": inf["kkt"]["maxresid"], "pobj": inf["kkt"]["pobj"],
+                   "levels": _level_times(s)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant)
+    s.configure(eps_rel=1e-8, time_limit_s=cap, variant=variant, levels=TTK_LEVELS)
     r = s.solve_refined(outer_eps=1e-8, inner_eps=1e-4, max_rounds=12,
                         max_inner_iters=5_000_000)
     torch.cuda.synchronize()
@@ -168,7 +186,8 @@ def time_to_kkt(s, lp, cap, variant, tag):
     res["fp32_refine"] = {"seconds": round(t, 3), "status": r["status"],
                           "cap_s": round(cap, 1), "rounds": r["rounds"],
                           "inner_iters": r["inner_iters"],
-                          "maxresid": r["kkt"]["maxresid"], "pobj": r["kkt"]["pobj"]}
+                          "maxresid": r["kkt"]["maxresid"], "pobj": r["kkt"]["pobj"],
+                          "levels": _level_times(s)}
     if res["fp64"]["status"] == 1 and res["fp32_refine"]["status"] == 1:
         res["speedup_fp32_refine"] = round(res["fp64"]["seconds"] /
                                            res["fp32_refine"]["seconds"], 3)

@@ -228,6 +228,14 @@ class Solver:
                 self.ctx)
         return inf.asdict(), x, y, z
 
+    def snapshot_info(self, idx: int) -> dict:
+        """pdhg_snapshot without the vectors: level, iteration, maxresid and
+        wall time of snapshot idx."""
+        inf = L.SnapInfo()
+        L.check(self.lib.pdhg_snapshot(self.ctx, idx, C.byref(inf), None, None, None,
+                                       L.MEM_HOST), self.ctx)
+        return inf.asdict()
+
     def set_snapshot_callback(self, fn, with_vectors: bool = False):
         """fn(idx, info_dict) -- or, with_vectors, fn(idx, info_dict, x, y, z)
         with copies of the snapshot's unscaled vectors -- runs on a library

@@ -252,6 +252,7 @@ def test_full_solve_kkt_and_snapshots(Solver, oracle, variant, panels):
     assert s.snapshot_count() == len(ref.snaps) == 2
     for i, sn in enumerate(ref.snaps):
         info, x, y, z = s.snapshot(i)
+        assert s.snapshot_info(i) == info           # the call without vectors
         assert info["level"] == sn["level"] and info["iter"] == sn["iter"]
         assert abs(info["maxresid"] - sn["maxresid"]) <= 1e-12
         assert err(x, ref.snap_x[i]) <= 1e-8 and err(y, ref.snap_y[i]) <= 1e-8
