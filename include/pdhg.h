@@ -163,10 +163,10 @@ typedef struct {
                                    progress * maxresid before the round) (1e-2) */
     int32_t inner_precision;    /* PDHG_FP32 (default) or PDHG_FP64 inner solves */
     int32_t omega_carry;        /* 1: a round starts from the final primal
-                                   weight of the last round whose inner solve
-                                   converged, times (D_D/D_D,then) /
-                                   (D_P/D_P,then); 0: from ||c^||/||b^|| of
-                                   the correction LP (1) */
+                                   weight of round 0 or of the last later
+                                   round whose inner solve converged, times
+                                   (D_D/D_D,then) / (D_P/D_P,then); 0: from
+                                   ||c^||/||b^|| of the correction LP (1) */
     int64_t stall_iters;        /* a round ends early once the refined point
                                    has not improved for max(stall_iters, 4 x
                                    the iterations it took to reach its best)
@@ -428,8 +428,9 @@ int pdhg_concurrent_crossover_refined(pdhg_ctx *ctx, pdhg_crossover_fn fn,
  * final one, if better) when that improves on the maxresid before the round:
  * partial progress is kept.  A round that cannot improve ends the refinement
  * (status PDHG_ITER_LIMIT).  With omega_carry, a round after the first starts
- * from the final primal weight of the last round whose inner solve converged,
- * rescaled by the change of Delta_D / Delta_P since then.
+ * from the final primal weight of round 0 or of the last later round whose
+ * inner solve converged, rescaled by the change of Delta_D / Delta_P since
+ * then.
  * Uses the parameters of the last configure (its
  * precision field is ignored; its time_limit_s bounds the whole
  * refinement).  The configured snapshot levels apply to the refined iterate:

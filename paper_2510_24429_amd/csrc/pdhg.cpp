@@ -2244,9 +2244,9 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
     const std::vector<double> saved_levels = c->levels;
     const int saved_slots = c->n_slots;
     double DP = 1.0, DD = 1.0;
-    // primal weight at the end of the last round whose inner solve converged,
-    // with that round's scales (a round cut at its budget or for a stall may
-    // end with a weight far off the correction LP's)
+    // primal weight at the end of round 0 or of the last round whose inner
+    // solve converged, with that round's scales (a correction round cut at
+    // its budget or for a stall may end with a weight far off its LP's)
     double omega_ref = 0.0, DP_ref = 1.0, DD_ref = 1.0;
     int status = PDHG_ITER_LIMIT, r = 0;
     int64_t inner_total = 0;
@@ -2406,7 +2406,9 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
                 c->status = PDHG_RUNNING;
             }
             c->ref_target = -1.0;
-            if (c->status == PDHG_CONVERGED) {
+            // round 0 solves the LP itself: its weight is PDHG's own estimate
+            // for the LP however the round ended
+            if (c->status == PDHG_CONVERGED || r == 0) {
                 omega_ref = c->st_host->omega;
                 DP_ref = DP;
                 DD_ref = DD;
