@@ -394,8 +394,10 @@ typedef int (*pdhg_crossover_fn)(void *user, int idx,
  * reaches eps_rel without a winner, `fn` also runs on the calling thread from
  * the final iterate (idx -1) unless a snapshot was taken from that same
  * iterate.  *winner is -2 if no call succeeded.  *status receives the PDHG
- * status (PDHG_CANCELLED when a crossover won first).  Returns after every
- * crossover thread has finished. */
+ * status (PDHG_CANCELLED when a crossover won first).  A pdhg_cancel from
+ * another thread during the call stops PDHG and sets *cancel for the
+ * crossovers too; a cancel requested before the call is dropped.  Returns
+ * after every crossover thread has finished. */
 int pdhg_concurrent_crossover(pdhg_ctx *ctx, pdhg_crossover_fn fn, void *user,
                               int max_threads, int64_t max_iters,
                               int *winner, int *status);

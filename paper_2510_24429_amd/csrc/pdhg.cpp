@@ -2069,7 +2069,8 @@ int pdhg_kernel_times(pdhg_ctx *c, pdhg_kernel_time *out, int cap, int *count,
 namespace {
 
 bool refine_params_ok(const pdhg_refine_params &R);
-void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *info);
+void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *info,
+                 bool clear_cancel = true);
 
 // Algorithm 1 (Section 3.1) around a solve: `drive` runs it and returns the
 // PDHG status; every snapshot it records (and any recorded before) launches
@@ -2128,6 +2129,9 @@ int crossover_harness(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
         jobs.push([&run_job, jb] { run_job(jb); });
     };
     int st = c->status;
+    // a cancel left from an earlier call is dropped here, before any
+    // crossover can win; the solve `drive` runs keeps the flag as it is
+    c->cancel_flag.store(0);
     try {
         for (size_t i = 0; i < c->snaps.size() && !cancelled(); ++i) queue((int)i);
         c->snap_hook = [&](int before) {
@@ -2136,6 +2140,11 @@ int crossover_harness(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
         };
         st = drive();
         c->snap_hook = nullptr;
+        if (st == PDHG_CANCELLED) {
+            // a cancel from outside (pdhg_cancel) ends the crossovers too
+            __atomic_store_n(&cancel_word, 1, __ATOMIC_RELEASE);
+            jobs.notify();
+        }
         // Algorithm 1's last line: crossover from the converged iterate on
         // this thread, unless that iterate was already handed out
         if (!cancelled() && st == PDHG_CONVERGED &&
@@ -2155,6 +2164,7 @@ int crossover_harness(pdhg_ctx *c, pdhg_crossover_fn fn, void *user,
         __atomic_store_n(&cancel_word, 1, __ATOMIC_RELEASE);
         jobs.notify();
         jobs.close_and_join();
+        c->cancel_flag.store(0);
         throw;
     }
     jobs.close_and_join();
@@ -2200,7 +2210,7 @@ int pdhg_concurrent_crossover_refined(pdhg_ctx *c, pdhg_crossover_fn fn,
     if (!refine_params_ok(R)) return fail(c, PDHG_E_ARG, "invalid refinement parameters");
     return crossover_harness(c, fn, user, max_threads, [&]() {
         pdhg_refine_info ri;
-        refine_impl(c, R, &ri);
+        refine_impl(c, R, &ri, false);
         if (info) *info = ri;
         return (int)ri.status;
     }, winner, status);
@@ -2219,8 +2229,11 @@ bool refine_params_ok(const pdhg_refine_params &R) {
 }
 
 // The refinement driver behind pdhg_solve_refined (R already checked);
-// throws DevError on device errors.
-void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *info) {
+// throws DevError on device errors.  clear_cancel: drop a cancel requested
+// before the call (false under the crossover harness, whose winner may have
+// cancelled already).
+void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *info,
+                 bool clear_cancel) {
     const bool in64 = R.inner_precision == PDHG_FP64;
     const double *ls = c->has_l ? c->ls : nullptr;
     const double t0 = now_s();
@@ -2256,7 +2269,7 @@ void refine_impl(pdhg_ctx *c, const pdhg_refine_params &R, pdhg_refine_info *inf
     c->snaps.clear();
     c->keep_snaps = true;
     // a cancel is kept across the inner solves (each would clear it)
-    c->cancel_flag.store(0);
+    if (clear_cancel) c->cancel_flag.store(0);
     c->keep_cancel = true;
     // snapshots of the refined iterate at the configured levels, taken
     // whenever its FP64 maxresid is measured (before every round and at the

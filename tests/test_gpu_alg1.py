@@ -152,3 +152,50 @@ def test_busy_threads_do_not_hold_up_pdhg(Solver):
     assert all(a <= 2 for _, a in starts)
     assert dt >= 4 * 0.4
     assert t_iter < 0.8, t_iter
+
+
+def test_outside_cancel_reaches_the_crossovers(Solver):
+    """pdhg_cancel from another thread during the harness stops PDHG and sets
+    the crossovers' cancel word: a crossover that waits for it returns, and
+    the call ends with PDHG_CANCELLED and no winner."""
+    lp = lpgen.planted_uniform(m=20000, n=60000, k=5, seed=4)
+    started, saw = threading.Event(), []
+
+    def crossover(idx, info, x, y, z, cancelled):
+        started.set()
+        t0 = time.time()
+        while not cancelled() and time.time() - t0 < 30:
+            time.sleep(0.005)
+        saw.append(cancelled())
+        return False
+
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-12, levels=[1e-2], max_iters=2_000_000)
+
+        def cancel_once_started():
+            if started.wait(30):
+                s.cancel()
+
+        th = threading.Thread(target=cancel_once_started)
+        th.start()
+        t0 = time.time()
+        winner, status = s.concurrent_crossover(crossover)
+        dt = time.time() - t0
+        th.join()
+    assert status == 4 and winner == -2
+    assert saw == [True]
+    assert dt < 30
+
+
+def test_cancel_before_the_call_is_dropped(Solver):
+    """A cancel requested before the harness starts does not stop it."""
+    lp = lpgen.make("uniform_m500_n1k")
+    with Solver.from_lp(lp) as s:
+        s.configure(eps_rel=1e-6, levels=[1e-4])
+        s.cancel()
+        winner, status = s.concurrent_crossover(lambda *a: False)
+        assert status == 1 and winner == -2
+        s.configure(eps_rel=1e-6, levels=[1e-4])
+        s.cancel()
+        winner, status, info = s.concurrent_crossover_refined(lambda *a: False)
+        assert status == 1 and winner == -2 and info["status"] == 1
