@@ -194,3 +194,78 @@ def test_stream_bandwidth_is_measured():
     g1 = stream_bandwidth(1, 1 << 26, 2)
     g2 = stream_bandwidth(2, 1 << 26, 2)
     assert g1 > 0.1 and g2 > 0.1
+
+
+# ------------------------------------------------------- degenerate inputs
+# The shapes of the GPU path's degenerate tests: one constraint row, A = I,
+# tiny LPs whose optimum vertex enumeration finds, an empty row and column.
+
+def _cpu_solve(lp, eps, threads=2, **kw):
+    with CpuSolver.from_lp(lp, threads=threads) as s:
+        s.configure(eps_rel=eps, **kw)
+        st = s.solve()
+        x, y, _ = s.get_iterate()
+        return st, s.info(), x, y
+
+
+def _from_dense(A, b, c, name="dense"):
+    rows, cols = np.nonzero(A)
+    return lpgen.from_coo(A.shape[0], A.shape[1], rows, cols, A[rows, cols], b, c,
+                          name=name)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_one_row_lp_closed_form(variant):
+    # min c^T x s.t. a^T x = beta, x >= 0, a > 0: p* = beta * min_j c_j / a_j
+    rng = np.random.default_rng(7)
+    a = rng.uniform(0.5, 2.0, 9)
+    c = rng.uniform(1.0, 3.0, 9)
+    lp = _from_dense(a[None, :], np.array([2.5]), c)
+    st, inf, x, _ = _cpu_solve(lp, 1e-11, eval_every=8, variant=variant)
+    assert st == 1
+    pstar = 2.5 * np.min(c / a)
+    assert abs(inf["kkt"]["pobj"] - pstar) <= 1e-9 * (1 + pstar)
+    j = int(np.argmin(c / a))
+    assert abs(x[j] - 2.5 / a[j]) <= 1e-7
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_identity_matrix_closed_form(variant):
+    # A = I: x = b is the only feasible point and y = c
+    rng = np.random.default_rng(3)
+    b = rng.uniform(0.1, 1.0, 12)
+    c = rng.standard_normal(12)
+    lp = _from_dense(np.eye(12), b, c)
+    st, inf, x, y = _cpu_solve(lp, 1e-11, eval_every=4, variant=variant)
+    assert st == 1
+    assert np.max(np.abs(x - b)) <= 1e-9 and np.max(np.abs(y - c)) <= 1e-8
+
+
+@pytest.mark.parametrize("seed,shape", [(0, (2, 4)), (1, (3, 6)), (2, (4, 8))])
+def test_tiny_lps_match_vertex_enumeration(seed, shape):
+    from tests.bruteforce import lp_optimum
+    m, n = shape
+    lp = lpgen.tiny_dense(m, n, seed=100 * m + seed)
+    p, d, _, _ = lp_optimum(lp.dense(), lp.b, lp.c)
+    st, inf, _, _ = _cpu_solve(lp, 1e-10, threads=1, eval_every=16,
+                               max_iters=2_000_000, variant=1)
+    assert st == 1
+    assert abs(inf["kkt"]["pobj"] - p) <= 1e-8 * (1 + abs(p))
+    assert abs(inf["kkt"]["dobj"] - d) <= 1e-8 * (1 + abs(d))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_empty_row_and_column_match_oracle(oracle, variant):
+    base = lpgen.planted_uniform(m=60, n=120, k=4, seed=9)
+    A = base.dense()
+    A = np.vstack([np.zeros((1, A.shape[1])), A])
+    A = np.hstack([np.zeros((A.shape[0], 1)), A])
+    lp = _from_dense(A, np.concatenate([[0.0], base.b]), np.concatenate([[0.7], base.c]))
+    assert lp.a_rp[1] == 0 and lp.at_rp[1] == 0
+    ref = oracle.solve(lp, eps_rel=1e-9, eval_every=16, variant=variant)
+    st, inf, x, _ = _cpu_solve(lp, 1e-9, threads=3, eval_every=16, variant=variant)
+    assert st == 1 and ref.info["status"] == 1
+    assert inf["iters"] == ref.info["iters"]
+    for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
+        assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
+    assert x[0] == 0.0
