@@ -78,6 +78,11 @@ struct CbItem {
     int slot;                   // host copy the callback reads
     hipEvent_t ev;
     pdhg_snapshot_info info;    // copied at enqueue: the list may grow meanwhile
+    // taken at enqueue, under the callback lock: the slot table may be
+    // resized and the callback replaced while the item waits
+    const double *host;
+    pdhg_snapshot_cb cb;
+    void *user;
 };
 
 }  // namespace
@@ -927,10 +932,7 @@ void cb_worker(pdhg_ctx *c) {
         }
         (void)hipEventSynchronize(it.ev);
         (void)hipEventDestroy(it.ev);
-        if (c->cb) {
-            const double *x = c->host_snap[it.slot];
-            c->cb(c->cb_user, it.idx, &it.info, x, x + c->n, x + c->n + c->m);
-        }
+        if (it.cb) it.cb(it.user, it.idx, &it.info, it.host, it.host + c->n, it.host + c->n + c->m);
         {
             std::lock_guard<std::mutex> lk(c->cb_mu);
             --c->host_snap_busy[it.slot];
@@ -964,7 +966,11 @@ void collect_snapshots(pdhg_ctx *c) {
 // Snapshots [before, end) share the slot of the first: copy it to pinned host
 // memory on the copy stream and queue their callbacks behind the copy.
 void start_snapshot_copies(pdhg_ctx *c, int before) {
-    if (!c->cb || (int)c->snaps.size() == before) return;
+    {
+        std::lock_guard<std::mutex> lk(c->cb_mu);
+        if (!c->cb) return;
+    }
+    if ((int)c->snaps.size() == before) return;
     const int64_t len = 2 * c->n + c->m;
     const int slot = c->snaps[before].slot;
     {
@@ -978,13 +984,21 @@ void start_snapshot_copies(pdhg_ctx *c, int before) {
         }
         c->cb_done_cv.wait(lk, [c, slot] { return c->host_snap_busy[slot] == 0; });
     }
-    if (!c->host_snap[slot])
-        HIPC(hipHostMalloc((void **)&c->host_snap[slot], len * sizeof(double), hipHostMallocDefault));
+    double *host = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->cb_mu);
+        host = c->host_snap[slot];
+    }
+    if (!host) {
+        HIPC(hipHostMalloc((void **)&host, len * sizeof(double), hipHostMallocDefault));
+        std::lock_guard<std::mutex> lk(c->cb_mu);
+        c->host_snap[slot] = host;
+    }
     hipEvent_t ready, done;
     HIPC(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     HIPC(hipEventRecord(ready, c->stream));
     HIPC(hipStreamWaitEvent(c->copy_stream, ready, 0));
-    HIPC(hipMemcpyAsync(c->host_snap[slot], c->slots + (int64_t)slot * len,
+    HIPC(hipMemcpyAsync(host, c->slots + (int64_t)slot * len,
                         len * sizeof(double), hipMemcpyDeviceToHost, c->copy_stream));
     HIPC(hipEventCreateWithFlags(&done, hipEventDisableTiming));
     HIPC(hipEventRecord(done, c->copy_stream));
@@ -997,7 +1011,7 @@ void start_snapshot_copies(pdhg_ctx *c, int before) {
                 HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
                 HIPC(hipEventRecord(e, c->copy_stream));
             }
-            c->cb_queue.push_back({i, slot, e, c->snaps[i].info});
+            c->cb_queue.push_back({i, slot, e, c->snaps[i].info, host, c->cb, c->cb_user});
             ++c->host_snap_busy[slot];
         }
     }
@@ -1884,8 +1898,12 @@ int pdhg_snapshot(pdhg_ctx *c, int idx, pdhg_snapshot_info *info, double *x,
 
 int pdhg_set_snapshot_callback(pdhg_ctx *c, pdhg_snapshot_cb cb, void *user) {
     API_BEGIN(c)
-    c->cb = cb;
-    c->cb_user = user;
+    {
+        // snapshots already queued keep the callback they were queued with
+        std::lock_guard<std::mutex> lk(c->cb_mu);
+        c->cb = cb;
+        c->cb_user = user;
+    }
     if (cb && !c->cb_thread.joinable()) {
         c->cb_stop = false;
         c->cb_thread = std::thread(cb_worker, c);

@@ -171,16 +171,19 @@ def test_refinement_snapshots_of_refined_iterate(Solver, oracle, literal):
     import threading
     lp = lpgen.make("uniform_m500_n1k")
     levels = [1e-2, 1e-4, 1e-6, 1e-8]
-    seen, ev = [], threading.Event()
+    seen, got, ev = [], {}, threading.Event()
 
-    def cb(idx, info):
+    def cb(idx, info, x, y, z):
+        # the refinement adds host slots as it reaches levels while earlier
+        # callbacks may still run: each call gets its own snapshot's copy
         seen.append((idx, info["level"]))
+        got[idx] = (x, y, z)
         if len(seen) == len(levels):
             ev.set()
 
     with Solver.from_lp(lp) as s:
         s.configure(eps_rel=1e-8, levels=levels, literal_snapshots=literal)
-        s.set_snapshot_callback(cb)
+        s.set_snapshot_callback(cb, with_vectors=True)
         r = s.solve_refined(outer_eps=1e-8)
         assert r["status"] == 1
         # one level per measurement when literal, so not all may fire
@@ -193,6 +196,8 @@ def test_refinement_snapshots_of_refined_iterate(Solver, oracle, literal):
         iters = []
         for i in range(cnt):
             info, x, y, z = s.snapshot(i)
+            if i in got:
+                assert all(np.array_equal(a, b) for a, b in zip(got[i], (x, y, z)))
             assert info["level"] == levels[i]
             kk = oracle.kkt(lp, x, y, want_z=True)
             assert kk["maxresid"] <= info["level"]
