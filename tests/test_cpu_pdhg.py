@@ -269,3 +269,36 @@ def test_empty_row_and_column_match_oracle(oracle, variant):
     for key in ("rel_p", "rel_d", "rel_gap", "maxresid"):
         assert abs(inf["kkt"][key] - ref.kkt[key]) <= 1e-12, key
     assert x[0] == 0.0
+
+
+# ------------------------------------------------ LPs without an optimum
+# An infeasible LP (x1 + x2 = -1, x >= 0) drives y along its infeasibility
+# ray: the solve runs to its iteration limit with finite iterates.  An
+# unbounded LP (min -x1, x1 - x2 = 0, x >= 0) drives x along its ray, and the
+# primal-weight updates at restarts make the growth geometric until the
+# iterates overflow: the solve reports NUMERICAL.  There is no infeasibility
+# detection; both end as the oracle's do.
+
+NO_OPTIMUM = {
+    "infeasible": lambda: lpgen.from_coo(1, 2, [0, 0], [0, 1], [1.0, 1.0], [-1.0],
+                                         [1.0, 1.0], name="infeasible"),
+    "unbounded": lambda: lpgen.from_coo(1, 2, [0, 0], [0, 1], [1.0, -1.0], [0.0],
+                                        [-1.0, 0.0], name="unbounded"),
+}
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("kind", ["infeasible", "unbounded"])
+def test_lps_without_optimum_end_as_the_oracle(oracle, kind, variant):
+    lp = NO_OPTIMUM[kind]()
+    kw = dict(eps_rel=1e-8, eval_every=8, variant=variant)
+    assert _trace(oracle, lp, 100, threads=1, **kw) <= 1e-10
+    ref = oracle.solve(lp, max_iters=20000, **kw)
+    with CpuSolver.from_lp(lp, threads=1) as s:
+        s.configure(max_iters=20000, **kw)
+        st = s.solve()
+        assert st == ref.info["status"] == (2 if kind == "infeasible" else 5)
+        assert s.info()["iters"] == ref.info["iters"]
+        x, y, _ = s.get_iterate()
+        if kind == "infeasible":
+            assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))

@@ -105,3 +105,37 @@ def test_empty_row_and_column_match_oracle(Solver, oracle, variant):
     assert x[0] == 0.0
     pstar = base.c @ base.x_star
     assert abs(inf["kkt"]["pobj"] - pstar) <= 1e-7 * (1 + abs(pstar))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("kind", ["infeasible", "unbounded"])
+def test_lps_without_optimum_end_as_the_oracle(Solver, oracle, kind, variant):
+    """An infeasible LP (x1 + x2 = -1) runs to its iteration limit with finite
+    iterates; an unbounded one (min -x1, x1 = x2) grows until the iterates
+    overflow and reports NUMERICAL, as the oracle does; the first 100
+    iterates match the oracle's within 1e-10."""
+    if kind == "infeasible":
+        lp = lpgen.from_coo(1, 2, [0, 0], [0, 1], [1.0, 1.0], [-1.0], [1.0, 1.0])
+    else:
+        lp = lpgen.from_coo(1, 2, [0, 0], [0, 1], [1.0, -1.0], [0.0], [-1.0, 0.0])
+    kw = dict(eps_rel=1e-8, eval_every=8, variant=variant)
+    tr = oracle.solve(lp, trace_k=100, max_iters=100, **kw)
+    ref = oracle.solve(lp, max_iters=20000, **kw)
+    with Solver.from_lp(lp) as s:
+        s.configure(**kw)
+        for k in range(100):
+            s.iterate(1)
+            x, y, _ = s.get_iterate()
+            scale_x = max(np.max(np.abs(tr.trace_x[k])), 1e-300)
+            scale_y = max(np.max(np.abs(tr.trace_y[k])), 1e-300)
+            assert np.max(np.abs(x - tr.trace_x[k])) <= 1e-10 * scale_x, k
+            assert np.max(np.abs(y - tr.trace_y[k])) <= 1e-10 * scale_y, k
+        s.configure(max_iters=20000, **kw)
+        st = s.solve()
+        inf = s.info()
+    assert st == ref.info["status"] == (2 if kind == "infeasible" else 5)
+    if kind == "infeasible":
+        assert inf["iters"] == ref.info["iters"] == 20000
+    else:
+        # the evaluation at which a sum first overflows may differ by one
+        assert abs(inf["iters"] - ref.info["iters"]) <= kw["eval_every"]
