@@ -139,3 +139,24 @@ def test_lps_without_optimum_end_as_the_oracle(Solver, oracle, kind, variant):
     else:
         # the evaluation at which a sum first overflows may differ by one
         assert abs(inf["iters"] - ref.info["iters"]) <= kw["eval_every"]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("with_l", [False, True])
+def test_matrix_without_nonzeros(Solver, oracle, variant, with_l):
+    """A = 0 (3 x 4, no entries), b = 0, c > 0: no row block has work, the
+    power iteration falls back to 1, and x = max(0, l) is optimal; status,
+    iterations and x as the oracle's."""
+    e = np.array([], dtype=np.int64)
+    lp = lpgen.from_coo(3, 4, e, e, np.array([]), np.zeros(3),
+                        np.array([1.0, 2.0, 0.5, 1.0]), name="zero")
+    l = np.array([0.5, 0.0, 2.0, 1.0]) if with_l else None
+    kw = dict(eps_rel=1e-10, max_iters=1000, variant=variant)
+    ref = oracle.solve(lp, l=l, **kw)
+    with Solver.from_lp(lp, lb=l) as s:
+        s.configure(**kw)
+        assert s.info()["sigma_hat"] == ref.info["sigma_hat"] == 1.0
+        assert s.solve() == ref.info["status"] == 1
+        assert s.info()["iters"] == ref.info["iters"]
+        x, _, _ = s.get_iterate()
+    assert np.array_equal(x, np.zeros(4) if l is None else l)
