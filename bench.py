@@ -22,7 +22,9 @@ Also reported, outside the timed region:
     headline LP and on the power-law and multicommodity LPs, each run capped
     so the whole benchmark fits its time budget (status and maxresid at the
     cap are reported when 1e-8 is not reached);
-  - the multi-threaded CPU PDHG: iterations/s against the thread count.
+  - the multi-threaded CPU PDHG: iterations/s against the thread count;
+  - Algorithm 1's harness: PDHG iterations/s with crossover threads running
+    beside it, against the same iterations without them.
 """
 from __future__ import annotations
 
@@ -201,6 +203,39 @@ def time_to_kkt(s, lp, cap, variant, tag):
     res["fp32_refine"]["obj_rel_diff_vs_fp64"] = (
         abs(res["fp32_refine"]["pobj"] - p64) / (1 + abs(p64)))
     return res
+
+
+def alg1_harness_rate(s, variant, K=16384):
+    """Algorithm 1 (Section 3.1) with a stand-in crossover: PDHG iterations/s
+    over K iterations while the harness launches a crossover thread per
+    snapshot (each sleeps 0.2 s and reports no success), against the same K
+    iterations without the harness.  Rates from the library's own iteration
+    time (t_iter), so the wait for the last crossover is not counted."""
+    import threading
+    levels = [1e-2, 1e-3, 1e-4, 1e-5]
+    s.configure(eps_rel=1e-12, variant=variant, max_iters=K)
+    s.solve()
+    plain = s.info()
+    started, lock = [], threading.Lock()
+
+    def crossover(idx, info, x, y, z, cancelled):
+        with lock:
+            started.append(idx)
+        time.sleep(0.2)
+        return False
+
+    s.configure(eps_rel=1e-12, variant=variant, max_iters=K, levels=levels)
+    winner, status = s.concurrent_crossover(crossover)
+    harn = s.info()
+    r_plain = plain["iters"] / plain["t_iter"]
+    r_harn = harn["iters"] / harn["t_iter"]
+    log(f"alg1 harness: {r_harn:.1f} iters/s with {len(started)} crossovers, "
+        f"{r_plain:.1f} without")
+    return {"iters": K, "iters_s_plain": round(r_plain, 1),
+            "iters_s_with_harness": round(r_harn, 1),
+            "ratio": round(r_harn / r_plain, 4), "snapshots": s.snapshot_count(),
+            "crossovers_started": len(started), "winner": winner, "status": status,
+            "crossover": "stand-in: sleeps 0.2 s, never succeeds"}
 
 
 def cpu_model() -> str:
@@ -461,6 +496,7 @@ def main():
             log(f"powerlaw_m200k_n1m: {r1['iters_s']:.1f} iters/s")
             out["powerlaw_m200k_n1m"] = {"iters_s": round(r1["iters_s"], 2),
                                          "kernels": kernels_dict(r1)}
+            out["alg1_harness"] = alg1_harness_rate(s1, args.variant)
             if not args.no_ttk and left() > 150:
                 ttk["powerlaw_m200k_n1m"] = time_to_kkt(
                     s1, lp1, min(args.ttk_cap, 90.0), args.variant, "powerlaw")
